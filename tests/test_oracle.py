@@ -1,0 +1,311 @@
+"""Pins for the CPU oracle: each test checks the oracle against something other
+than itself -- hand-derived values (tests/golden), closed forms, exact
+enumeration, brute force, a textbook DP, a library Philox, high-precision
+arithmetic and the stationary distribution of Metropolis sampling."""
+import itertools
+import json
+import math
+import os
+import shutil
+import subprocess
+from decimal import Decimal, getcontext
+
+import numpy as np
+import pytest
+
+from paper_2608_25376_amd import inputs
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def golden(name):
+    with open(os.path.join(HERE, "golden", name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------- costs ----
+def test_cost_is_exact_rounding(oracle_lib):
+    """w = round(10 sqrt(q)) means (2w-1)^2 < 400 q < (2w+1)^2 (no ties exist
+    since 400q is even); check every displacement of a 40x40 field."""
+    for di in range(40):
+        for dj in range(40):
+            w = oracle_lib.cost(40, 0, di * 40 + dj, 10)
+            q = di * di + dj * dj
+            assert (2 * w - 1) ** 2 < 400 * q < (2 * w + 1) ** 2 or (q == 0 and w == 0)
+
+
+def test_cost_units_follow_paper_parameters(oracle_lib):
+    """5 m cells flown at 5 m/s: a unit step is 1 s (10 ds), a diagonal sqrt(2) s."""
+    p = golden("paper_params.json")
+    tau = 1.0 / p["speed_m_per_s"]
+    unit_s = p["cell_width_m"] * tau
+    assert unit_s == 1.0
+    assert oracle_lib.cost(3, 0, 1, 10) == round(10 * unit_s)
+    assert oracle_lib.cost(3, 0, 4, 10) == round(10 * unit_s * math.sqrt(2))
+
+
+# ----------------------------------------------------------------- QUBO ----
+def test_golden_2x2_qubo(oracle_lib):
+    g = golden("grid2x2.json")
+    q = oracle_lib.OracleQubo(2, 2)
+    assert q.m == g["m"]
+    assert q.W.tolist() == g["W"]
+    assert (q.wmax, q.P, q.c0) == (g["w_max"], g["P"], g["c0"])
+    assert q.b.tolist() == g["b"]
+
+
+def _all_states(N):
+    for v in range(1 << N):
+        yield np.array([(v >> k) & 1 for k in range(N)], np.uint8)
+
+
+@pytest.mark.parametrize("rows,cols,nofly,closed", [
+    (2, 2, None, True), (2, 2, None, False),
+    (2, 3, [0, 0, 1, 0, 0, 0], True),          # m = 4, N = 16
+    (3, 2, [0, 0, 0, 1, 0, 0], False),
+])
+def test_literal_equals_qubo_all_states(oracle_lib, rows, cols, nofly, closed):
+    """Eqs. (3)-(6) evaluated literally equal the expanded QUBO on every state."""
+    q = oracle_lib.OracleQubo(rows, cols, nofly=nofly, closed=closed)
+    assert q.N <= 16
+    for x in _all_states(q.N):
+        assert q.literal_energy(x) == q.energy(x)
+
+
+@pytest.mark.parametrize("side,dens,closed", [(3, 0.0, True), (5, 0.2, True), (6, 0.1, False), (8, 0.1, True)])
+def test_literal_equals_qubo_random_states(oracle_lib, side, dens, closed):
+    g = inputs.grid(side, side, dens, seed=7, inst=side)
+    q = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed)
+    rng = np.random.default_rng(3)
+    for p1 in (0.02, 0.1, 0.5):
+        for _ in range(6):
+            x = (rng.random(q.N) < p1).astype(np.uint8)
+            assert q.literal_energy(x) == q.energy(x)
+    # permutation states: energy equals the tour cost (penalties vanish)
+    for _ in range(5):
+        perm = rng.permutation(q.m)
+        x = np.zeros((q.m, q.m), np.uint8)
+        x[np.arange(q.m), perm] = 1
+        path = q.decode(x.reshape(-1))
+        assert q.energy(x.reshape(-1)) == q.path_cost(path)
+
+
+def test_qubo_structure(oracle_lib):
+    g = inputs.grid(6, 6, 0.1, seed=5, inst=1)
+    q = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly)
+    J, m = q.J, q.m
+    assert (J == J.T).all()
+    assert (np.diag(J) == 0).all()
+    # row (t,c): 2P to the m-1 others in step t and the m-1 others of cell c,
+    # w(c,c') to cells of the neighbouring steps (2P + 0 on the same cell)
+    for k in [0, m + 3, q.N - 1]:
+        t, c = divmod(k, m)
+        same_t = [t * m + c2 for c2 in range(m) if c2 != c]
+        same_c = [t2 * m + c for t2 in range(m) if t2 != t]
+        assert all(J[k, l] >= 2 * q.P for l in same_t + same_c)
+        nb = [l for l in range(q.N) if abs(l // m - t) == 1 and l % m != c]
+        for l in nb:
+            assert J[k, l] == q.W[c + 1, l % m + 1]
+        others = set(range(q.N)) - set(same_t) - set(same_c) - set(nb) - {k}
+        assert all(J[k, l] == 0 for l in others)
+
+
+# --------------------------------------------------------- ground states ---
+def test_2x2_enumeration_matches_brute_force(oracle_lib):
+    g = golden("grid2x2.json")
+    q = oracle_lib.OracleQubo(2, 2)
+    mn, cnt, arg, inf = q.enum_min()
+    assert mn == g["optimum"] and cnt == g["n_optimal"]
+    assert q.tour_brute() == (g["optimum"], g["n_optimal"])
+    assert q.held_karp() == g["optimum"]
+    assert q.decode(arg) is not None
+    # every infeasible state is at least 2 min(w_min, P - w_max) above the optimum
+    wmin = q.W[q.W > 0].min()
+    assert inf >= mn + 2 * min(wmin, q.P - q.wmax)
+
+
+def test_random_small_fields_ground_state_is_optimal_tour(oracle_lib):
+    """On fields with at most 4 free cells (N <= 16) the QUBO minimum equals
+    the brute-force tour optimum, and its minimisers are exactly the optimal
+    tours (one state each)."""
+    rng = np.random.default_rng(11)
+    done = 0
+    while done < 12:
+        rows, cols = int(rng.integers(2, 4)), int(rng.integers(2, 5))
+        nofly = (rng.random(rows * cols) < 0.5).astype(np.uint8)
+        nofly[0] = 0
+        m = rows * cols - 1 - int(nofly.sum())
+        if not 1 <= m <= 4:
+            continue
+        for closed in (True, False):
+            q = oracle_lib.OracleQubo(rows, cols, nofly=nofly, closed=closed)
+            mn, cnt, arg, inf = q.enum_min()
+            best, n_opt = q.tour_brute()
+            assert mn == best and cnt == n_opt
+            assert q.decode(arg) is not None
+            assert q.path_cost(q.decode(arg)) == mn
+            assert inf > mn
+        done += 1
+
+
+def test_3x3_optimum(oracle_lib):
+    g = golden("grid3x3.json")
+    q = oracle_lib.OracleQubo(3, 3)
+    assert (q.m, q.wmax, q.P, q.c0) == (g["m"], g["w_max"], g["P"], g["c0"])
+    assert q.tour_brute()[0] == g["optimum"]
+    assert q.held_karp() == g["optimum"]
+    assert q.path_cost(g["optimal_tour_rowmajor"]) == g["optimum"]
+
+
+def test_held_karp_equals_brute_force(oracle_lib):
+    for i in range(8):
+        g = inputs.grid(4, 4, 0.35, seed=21, inst=i)
+        for closed in (True, False):
+            q = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed, dense=False)
+            if 1 <= q.m <= 9:
+                assert q.held_karp() == q.tour_brute()[0]
+
+
+# ---------------------------------------------------------------- Philox ---
+def test_philox_matches_rocrand_header(oracle_lib, tmp_path):
+    """rocRAND ships Philox4x32-10 as a header; compile a host program against
+    it and compare on random counters/keys and edge values."""
+    hipcc = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
+    if not os.path.exists(hipcc):
+        pytest.skip("hipcc not available")
+    exe = tmp_path / "philox_pin"
+    subprocess.run([hipcc, "-O1", "-o", str(exe), os.path.join(HERE, "philox_pin.cpp")], check=True,
+                   capture_output=True)
+    rng = np.random.default_rng(5)
+    cases = [[0] * 6, [2 ** 32 - 1] * 6, [1, 2, 3, 4, 5, 6]]
+    cases += rng.integers(0, 2 ** 32, size=(60, 6)).tolist()
+    text = "\n".join(" ".join(str(int(v)) for v in c) for c in cases) + "\n"
+    res = subprocess.run([str(exe)], input=text, capture_output=True, text=True, check=True)
+    lines = res.stdout.strip().split("\n")
+    assert len(lines) == len(cases)
+    for c, line in zip(cases, lines):
+        ref = [int(v) for v in line.split()]
+        got = oracle_lib.philox(c[:4], c[4:]).tolist()
+        assert got == ref
+
+
+def test_philox_site_addressing_uniformity(oracle_lib):
+    """Acceptance words over many sites look uniform (mean, bit balance)."""
+    ws = np.array([oracle_lib.accept_word(1, 0, r, s, t, c) for r in range(4) for s in range(4)
+                   for t in range(1, 9) for c in range(16)], np.float64)
+    u = ws / 2.0 ** 32
+    assert abs(u.mean() - 0.5) < 0.03
+    assert abs((u < 0.25).mean() - 0.25) < 0.03
+    bits = [oracle_lib.init_bit(1, 0, r, t, c) for r in range(8) for t in range(1, 17) for c in range(16)]
+    assert abs(np.mean(bits) - 0.5) < 0.05
+
+
+# ------------------------------------------------------------ thresholds ---
+def test_thresholds_exact(oracle_lib):
+    """thr[s][d] = floor(2^32 exp(-d/T_s)) checked in 40-digit decimal
+    arithmetic; Dmax = floor(32 T0 ln 2) + 1."""
+    getcontext().prec = 40
+    for T0, T1, S in [(100.0, 0.5, 1000), (200.0, 0.5, 37)]:
+        dmax, thr = oracle_lib.thresholds(T0, T1, S)
+        assert dmax == math.floor(32 * T0 * math.log(2)) + 1
+        assert (thr[:, dmax] == 0).all()
+        rng = np.random.default_rng(1)
+        for s in list(rng.integers(0, S, 12)) + [0, S - 1]:
+            T = Decimal(repr(oracle_lib.temperature(T0, T1, S, int(s))))
+            for d in list(rng.integers(1, dmax + 1, 40)) + [1, 2, dmax - 1, dmax]:
+                exact = (Decimal(2) ** 32) * (-(Decimal(int(d)) / T)).exp()
+                fl = int(exact)  # floor for a positive value
+                got = int(thr[s, d])
+                frac = exact - fl
+                if Decimal("1e-9") < frac < 1 - Decimal("1e-9"):
+                    assert got == min(fl, 2 ** 32 - 1)
+                else:
+                    assert abs(got - fl) <= 1
+        # geometric schedule end points and monotonicity
+        assert oracle_lib.temperature(T0, T1, S, 0) == T0
+        assert abs(oracle_lib.temperature(T0, T1, S, S - 1) - T1) < 1e-12
+        assert (np.diff(thr[:, 1:].astype(np.int64), axis=1) <= 0).all()
+        assert (np.diff(thr[:, 1:].astype(np.int64), axis=0) <= 0).all()
+
+
+# --------------------------------------------------------------- annealer --
+def test_anneal_invariants(oracle_lib):
+    """Incremental fields equal a recomputed Qx and E after every sweep; the
+    returned energies equal both QUBO and literal evaluations."""
+    for side, dens, closed in [(3, 0.0, True), (4, 0.2, True), (5, 0.1, False)]:
+        g = inputs.grid(side, side, dens, seed=2, inst=side)
+        q = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed)
+        r = oracle_lib.anneal(q, 40, 60.0, 0.5, 3, g.inst_id, list(range(6)), check_every=1)
+        assert (r["mismatches"] == 0).all()
+        for i in range(6):
+            assert r["final_E"][i] == q.energy(r["final_x"][i]) == q.literal_energy(r["final_x"][i])
+            assert r["best_E"][i] == q.energy(r["best_x"][i])
+            assert 0 <= r["best_sweep"][i] < 40
+        assert (r["draws"] > 0).all() and (r["accepts"] > 0).all()
+
+
+def test_anneal_finds_optimum_and_decodes(oracle_lib):
+    q = oracle_lib.OracleQubo(3, 3)
+    reps = list(range(1024))
+    r = oracle_lib.anneal(q, 1000, 100.0, 0.5, 1, 0, reps, threads=8)
+    best = oracle_lib.instance_best(r, reps)
+    assert best["best_E"] == golden("grid3x3.json")["optimum"]
+    path = q.decode(best["best_x"])
+    assert path is not None and q.path_cost(path) == best["best_E"]
+    # states within 1% of the optimum are feasible here (penalty 2 w_max)
+    near = r["best_E"] * 100 <= 101 * best["best_E"]
+    assert all(q.decode(x) is not None for x in r["best_x"][near])
+
+
+def test_anneal_zero_temperature_descent(oracle_lib):
+    """At T -> 0 only non-increasing moves are taken: E after s sweeps is
+    non-increasing in s and never above the initial energy."""
+    g = inputs.grid(4, 4, 0.1, seed=4, inst=0)
+    q = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly)
+    Es = []
+    for S in range(1, 9):
+        r = oracle_lib.anneal(q, S, 1e-3, 1e-3, 9, 0, [0, 1, 2])
+        assert (r["draws"] == 0).all()
+        Es.append(r["final_E"])
+    Es = np.array(Es)
+    assert (np.diff(Es, axis=0) <= 0).all()
+
+
+def test_anneal_checkpoint_split(oracle_lib):
+    """The stream is addressed by (instance, replica, sweep, site), so stopping
+    after S1 sweeps and resuming from that state at sweep S1 gives the same
+    trajectory as one straight run."""
+    g = inputs.grid(4, 4, 0.0, seed=1, inst=3)
+    q = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly)
+    table = oracle_lib.thresholds(80.0, 0.5, 60)
+    reps = [0, 5, 9]
+    full = oracle_lib.anneal(q, 60, 80.0, 0.5, 4, 3, reps, table=table)
+    # first leg: the same schedule rows, stopped after 25 sweeps
+    dmax, thr = table
+    first = oracle_lib.anneal(q, 25, 80.0, 0.5, 4, 3, reps, table=(dmax, thr[:25].copy()))
+    second = oracle_lib.anneal(q, 60, 80.0, 0.5, 4, 3, reps, init_x=first["final_x"], start_sweep=25,
+                               table=table)
+    assert (second["final_x"] == full["final_x"]).all()
+    assert (second["final_E"] == full["final_E"]).all()
+    assert (first["accepts"] + second["accepts"] == full["accepts"]).all()
+    assert (np.minimum(first["best_E"], second["best_E"]) == full["best_E"]).all()
+
+
+def test_anneal_boltzmann_stationary(oracle_lib):
+    """Sequential-sweep Metropolis leaves the Boltzmann distribution invariant:
+    at a fixed temperature, the final states of many independent replicas on
+    the 2x2 field (9 variables) follow exp(-E/T)/Z computed by enumeration."""
+    q = oracle_lib.OracleQubo(2, 2)
+    T = 40.0
+    S = 30
+    R = 40000
+    r = oracle_lib.anneal(q, S, T, T, 17, 0, list(range(R)), threads=8)
+    codes = (r["final_x"].astype(np.int64) << np.arange(q.N)).sum(1)
+    emp = np.bincount(codes, minlength=1 << q.N) / R
+    E = np.array([q.energy(x) for x in _all_states(q.N)], np.float64)
+    p = np.exp(-(E - E.min()) / T)
+    p /= p.sum()
+    tv = 0.5 * np.abs(emp - p).sum()
+    assert tv < 0.03, tv
+    # and a wrong sign in the acceptance rule would invert the ordering
+    assert emp[np.argmin(E)] > emp[np.argmax(E)]
