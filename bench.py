@@ -1,0 +1,147 @@
+"""Benchmark: spin-flip attempts per second of the MI355X annealer.
+
+One step = one full anneal_batch of the workload (replica initialisation,
+all sweeps, per-instance reduction) with the plan's static data already
+resident in HBM.  Prints one JSON line.
+
+Default workload: 8x8 field with Bernoulli(0.1) no-fly cells (54 free cells,
+2916 variables), 1024 replicas, 2000 sweeps, geometric T 200 -> 0.5, seed 1.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published figures and the integer-VALU peak derived from unit counts:
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 int32 lane-ops/s.
+PEAK_ALU_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic integer operations of the structured Metropolis step
+# ("Roofline"): per attempted flip, per random draw, per
+# accepted flip (plus m for the O(m) travel-row update).
+OPS_PER_ATTEMPT = 11
+OPS_PER_DRAW = 27
+OPS_PER_ACCEPT_BASE = 5
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="grid8x8_nofly0.1")
+    ap.add_argument("--kernel", default="factored", choices=["factored", "dense"])
+    ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-replicas", type=int, default=0, help="oracle sample size (0 = auto)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, q_gpu_m, args):
+    """The oracle as it stands, on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    g = w.grids[0]
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+    o = oracle.OracleQubo(g.rows, g.cols, nofly=g.nofly)
+    table = oracle.thresholds(w.T0, w.T1, w.sweeps)
+    # calibrate: one replica, then size the sample for ~15 s of work
+    reps = args.cpu_replicas
+    if reps <= 0:
+        t0 = time.perf_counter()
+        oracle.anneal(o, w.sweeps, w.T0, w.T1, w.seed, g.inst_id, [0], table=table, threads=1)
+        one = time.perf_counter() - t0
+        reps = int(max(threads, min(w.replicas, round(15.0 * threads / max(one, 1e-3)))))
+    t0 = time.perf_counter()
+    oracle.anneal(o, w.sweeps, w.T0, w.T1, w.seed, g.inst_id, list(range(reps)), table=table, threads=threads)
+    dt = time.perf_counter() - t0
+    attempts = reps * w.sweeps * o.N
+    return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "sample": f"{reps} of {w.replicas} replicas x {w.sweeps} sweeps of the same instance "
+                      f"({attempts:.3g} attempts, {dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(the annealer shards by instance/replica with no communication; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    from paper_2608_25376_amd import inputs, uavq
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    w = inputs.workload(args.workload)
+    dense = args.kernel == "dense"
+    qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly, dense=dense) for g in w.grids]
+    plan = uavq.Plan(qs, [g.inst_id for g in w.grids], w.replicas, w.sweeps, w.T0, w.T1, w.seed, dense=dense,
+                     waves_per_block=args.waves_per_block)
+    plan.upload()
+    out = plan.alloc_outputs()
+    plan.set_timing(True)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        plan.anneal(out=out)
+    torch.cuda.synchronize()
+
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    sweep_ms = []
+    torch.cuda.synchronize()
+    start.record(stream)
+    for _ in range(args.steps):
+        plan.anneal(out=out)
+        # the library's events bracket the sweep kernel of this call
+        torch.cuda.current_stream().synchronize()
+        sweep_ms.append(plan.sweep_ms())
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    ms_per_step = total_ms / args.steps
+
+    n_vars = sum(q.n_vars for q in qs)
+    attempts = float(sum(q.n_vars for q in qs) * w.replicas * w.sweeps)
+    acc = out.accepts.cpu().numpy().astype(np.float64)
+    drw = out.draws.cpu().numpy().astype(np.float64)
+    m_per_rep = np.concatenate([np.full(w.replicas, q.m) for q in qs]).astype(np.float64)
+    ops = OPS_PER_ATTEMPT * attempts + OPS_PER_DRAW * drw.sum() + ((m_per_rep + OPS_PER_ACCEPT_BASE) * acc).sum()
+    sweep_avg = float(np.mean(sweep_ms))
+    achieved = ops / (sweep_avg * 1e-3)
+    value = attempts / (ms_per_step * 1e-3)
+
+    res = {
+        "metric": "spin-flip attempts/s",
+        "value": value,
+        "unit": "attempts/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": w.name, "instances": len(qs), "m": int(qs[0].m) if len(qs) == 1 else None,
+                   "n_vars": n_vars, "replicas": w.replicas, "sweeps": w.sweeps, "T0": w.T0, "T1": w.T1,
+                   "seed": w.seed, "kernel": args.kernel, "attempts_per_step": attempts,
+                   "accept_rate": float(acc.sum() / attempts), "draw_rate": float(drw.sum() / attempts),
+                   "best_E": [int(v) for v in out.inst_best_E.cpu().numpy()[:4]]},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12,
+                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / PEAK_ALU_OPS, "traffic": None,
+                     "kernel": "k_sweep_factored" if not dense else "k_sweep_dense",
+                     "kernel_ms": sweep_avg, "ops_per_launch": ops},
+    }
+    if not args.no_cpu_baseline:
+        res["cpu_baseline"] = cpu_baseline(w, qs[0].m, args)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,218 @@
+/*
+ * uavq.h -- C ABI of the MI355X annealer for the UAV coverage-path QUBO.
+ *
+ * Method (paper: "GPU-Accelerated Quantum Annealing-Inspired UAV Path Planning
+ * for Smart Agriculture"): a field of M x N square cells (Sec. II) is covered
+ * by a tour that starts at cell c_{0,0}; the tour is written as a one-hot,
+ * time-indexed QUBO H = H_dist + P (H_visit + H_time) (Sec. III-B, eqs.
+ * (3)-(6)) and minimised by parallel annealing over many independent replicas
+ * (Sec. III-C, Alg. 1, Sec. IV-A).  This library builds that QUBO
+ * (uavq_qubo_build), anneals batches of instances on the GPU
+ * (uavq_anneal_batch) and evaluates energies (uavq_energy_eval).
+ *
+ * Conventions
+ *   - Every function returns 0 (UAVQ_OK) or a negative UAVQ_E* code; the
+ *     message of the last failure on the calling thread is uavq_last_error().
+ *     On failure no output buffer is written unless stated otherwise.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory owned by the caller (the library never frees them).
+ *   - Handles (uavq_qubo, uavq_plan) are created and freed by the library and
+ *     are immutable after creation; they may be shared between threads.
+ *   - Streams are hipStream_t passed as void*; NULL is the default stream.
+ *     uavq_anneal_batch and uavq_energy_eval_dev are asynchronous on it.
+ *
+ * Variables and states
+ *   m = number of cells to visit (free cells: not the start cell, not
+ *   no-fly), listed in increasing row-major index (the free list F).  The
+ *   variable x_{t,c} (step t = 1..m, free cell c = 0..m-1) is 1 when the tour
+ *   is at F[c] at step t; steps 0 and m+1 are fixed at the start cell (the
+ *   fixed start of Sec. II; the closed tour returns to it).  N = m*m.
+ *   Packed state: m rows of W = ceil(m/32) uint32 words; bit (c & 31) of
+ *   word (t-1)*W + (c >> 5) is x_{t,c}; unused high bits are zero.
+ *   state_words = m * W.
+ */
+#ifndef UAVQ_H
+#define UAVQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    UAVQ_OK = 0,
+    UAVQ_EINVAL = -1,       /* invalid argument */
+    UAVQ_ENOMEM = -2,       /* host allocation failed */
+    UAVQ_EHIP = -3,         /* a HIP runtime call failed (message names it) */
+    UAVQ_ETOOBIG = -4,      /* the instance exceeds a kernel's limits */
+    UAVQ_EINFEASIBLE = -5   /* a state is not a permutation matrix */
+};
+
+/* Message for the last error on this thread ("" if none).  Static storage. */
+const char *uavq_last_error(void);
+
+/* ABI version (major*100 + minor). */
+int32_t uavq_version(void);
+
+/* ------------------------------------------------------------------ QUBO -- */
+
+#define UAVQ_OPEN_PATH 0x1u   /* no return leg (eq. (1a) as printed); default closed tour */
+#define UAVQ_DENSE     0x2u   /* also keep the dense int16 J (needed by the dense kernel) */
+
+typedef struct {
+    int32_t rows, cols;       /* M, N of Sec. II; rows*cols <= 65536 */
+    int32_t depot;            /* row-major index of the start cell (c_{0,0} = 0) */
+    const uint8_t *nofly;     /* host, rows*cols bytes, 1 = excluded; NULL = none */
+    int32_t cost_scale;       /* w = round(cost_scale * distance in cells); 0 -> 10
+                                 (deciseconds for 5 m cells at 5 m/s, Sec. IV-C) */
+    int32_t penalty;          /* P; 0 -> 2 * w_max; otherwise must exceed w_max */
+    uint32_t flags;           /* UAVQ_OPEN_PATH | UAVQ_DENSE */
+} uavq_grid;
+
+typedef struct uavq_qubo uavq_qubo;
+
+typedef struct {
+    int32_t m;                /* free cells = steps */
+    int32_t n_vars;           /* N = m*m */
+    int32_t P;                /* one-hot penalty weight */
+    int32_t w_max;            /* largest travel cost between visit-list cells */
+    int64_t c0;               /* constant term, 2*P*m */
+    int32_t closed;           /* 1 = closed tour */
+    int32_t has_dense;        /* dense J kept */
+    int32_t row_words;        /* W = ceil(m/32) */
+    int32_t state_words;      /* m * W */
+} uavq_qubo_info_t;
+
+/* qubo_build -- Sec. II (grid, travel times t_ij = d_ij tau) and Sec. III-B
+ * eqs. (3)-(6) expanded with x^2 = x:
+ *   E(x) = c0 + sum_k b_k x_k + sum_{k<l} J_kl x_k x_l,
+ *   c0 = 2 P m,  b_{t,c} = -2P + [t=1] w(s,c) + [t=m, closed] w(c,s),
+ *   J_{(t,c),(t',c')} = 2P [t=t'] + 2P [c=c'] + w(c,c') [|t-t'| = 1]
+ * (s = start cell).  The handle keeps the free list, the cost matrix D
+ * (m x m) and the start-cell costs, and the dense J when UAVQ_DENSE is set.
+ * Errors: EINVAL for a bad grid (no free cell, start cell no-fly, penalty <=
+ * w_max, rows*cols > 65536), ETOOBIG when w_max > 255 (D is stored as bytes)
+ * or, with UAVQ_DENSE, when N > 46340 or 2P > 32767. */
+int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out);
+void uavq_qubo_free(uavq_qubo *q);
+int uavq_qubo_info(const uavq_qubo *q, uavq_qubo_info_t *info);
+/* Host copies: F (m grid indices); costs ((m+1)^2, index 0 = start cell). */
+int uavq_qubo_free_cells(const uavq_qubo *q, int32_t *F);
+int uavq_qubo_costs(const uavq_qubo *q, int32_t *W);
+/* Host export of b (N) and, if J != NULL, the dense J (N*N, row-major). */
+int uavq_qubo_export(const uavq_qubo *q, int32_t *b, int32_t *J);
+
+/* ---------------------------------------------------------------- energy -- */
+
+/* energy_eval -- E(x) of n_states packed host states (eqs. (3)-(6) through the
+ * expanded form), written to E (host, n_states). */
+int uavq_energy_eval(const uavq_qubo *q, const uint32_t *x_packed, int64_t n_states, int64_t *E);
+
+/* energy_eval on the device: E for n_states packed device states (contiguous,
+ * state_words apart) computed by the MFMA refresh kernel; d_E is device
+ * int64[n_states].  d_ws must hold uavq_energy_workspace_bytes() bytes. */
+int uavq_energy_workspace_bytes(const uavq_qubo *q, size_t *bytes);
+int uavq_energy_eval_dev(const uavq_qubo *q, const uint32_t *d_x_packed, int64_t n_states, int64_t *d_E,
+                         void *d_ws, size_t ws_bytes, void *stream);
+
+/* Path reconstruction (Alg. 1, last step): for a permutation state, path[0..m+1]
+ * (grid indices: start, the visited cells in order, start again; for an open
+ * path path[m+1] = -1) and its travel cost.  EINFEASIBLE otherwise. */
+int uavq_decode_path(const uavq_qubo *q, const uint32_t *x_packed, int32_t *path, int64_t *cost);
+
+/* -------------------------------------------------------------- schedule -- */
+
+/* Geometric temperatures T_s = T0 (T1/T0)^(s/(S-1)) and the acceptance table
+ * thr[s][d] = min(2^32-1, floor(2^32 exp(-d/T_s))), d = 0..Dmax (column 0
+ * unused), Dmax = least d with floor(2^32 exp(-d/T0)) = 0.  Pass thr = NULL to
+ * query Dmax; otherwise thr holds S*(Dmax+1) uint32 (host).  Requires
+ * 0 < T1 <= T0, S >= 1. */
+int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr);
+
+/* ------------------------------------------------------------- annealing -- */
+
+#define UAVQ_KERNEL_DENSE 0x1u   /* use the dense-field kernel (every qubo needs UAVQ_DENSE) */
+
+typedef struct {
+    int32_t replicas;         /* replicas per instance, >= 1 */
+    int32_t sweeps;           /* S >= 1 */
+    double T0, T1;            /* schedule end points, 0 < T1 <= T0 */
+    uint32_t seed;            /* random-stream key */
+    uint32_t flags;           /* UAVQ_KERNEL_DENSE */
+    int32_t waves_per_block;  /* replicas per workgroup; 0 = library choice.
+                                 Never changes results. */
+} uavq_anneal_params;
+
+typedef struct uavq_plan uavq_plan;
+
+/* Plan for annealing n_inst instances (ids inst_ids[i], which address the
+ * random streams, so an instance gives the same result alone or in a batch).
+ * Builds the schedule table and packs all static data on the host. */
+int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *inst_ids,
+                     const uavq_anneal_params *p, uavq_plan **out);
+void uavq_plan_free(uavq_plan *plan);
+
+typedef struct {
+    size_t ws_bytes;          /* device workspace needed */
+    int64_t total_replicas;   /* n_inst * replicas */
+    int64_t total_state_words;/* sum over instances of replicas * state_words */
+    int32_t n_inst;
+    int32_t Dmax;
+} uavq_plan_info_t;
+int uavq_plan_info(const uavq_plan *plan, uavq_plan_info_t *info);
+/* Replica r of instance i is global replica rep_offset[i] + r; its packed
+ * state starts at word state_offset[i] + r * state_words(i).  Arrays of
+ * n_inst + 1 entries (host). */
+int uavq_plan_layout(const uavq_plan *plan, int64_t *rep_offset, int64_t *state_offset);
+
+/* Copy the plan's static data (schedule table, cost matrices, dense J) into
+ * the device workspace.  Must precede uavq_anneal_batch on that workspace. */
+int uavq_plan_upload(const uavq_plan *plan, void *d_ws, size_t ws_bytes, void *stream);
+
+typedef struct {              /* optional device inputs (NULL = unused) */
+    const uint32_t *states;   /* total_state_words: initial states */
+    const uint8_t *seeded;    /* total_replicas: 1 = start from states[], 0 = random bits */
+    const int32_t *start_sweep; /* total_replicas: first sweep of that replica (0..S) */
+} uavq_anneal_init;
+
+typedef struct {              /* device outputs, caller-owned; NULL = not wanted */
+    uint32_t *final_states;   /* total_state_words (required: also the working state) */
+    int64_t *final_E;         /* total_replicas (required) */
+    int64_t *best_E;          /* total_replicas (required) */
+    int32_t *best_sweep;      /* total_replicas (required) */
+    uint32_t *best_states;    /* total_state_words (required) */
+    uint64_t *accepts;        /* total_replicas (required) */
+    uint64_t *draws;          /* total_replicas (required): random draws taken */
+    int64_t *inst_best_E;     /* n_inst */
+    int32_t *inst_best_replica;
+    int32_t *inst_best_sweep;
+    uint32_t *inst_best_state;/* total over instances of state_words */
+    int64_t *check_E;         /* total_replicas: E(final state) recomputed by the refresh */
+} uavq_anneal_out;
+
+/* anneal_batch -- single-flip Metropolis annealing of every replica:
+ *   x <- initial state (Bernoulli(1/2) bits from random stream 1, or given);
+ *   for s = start..S-1, for k = 0..N-1 in step-major order:
+ *     dE = (1 - 2 x_k) h_k,  h_k = b_k + sum_{l != k} J_kl x_l;
+ *     accept if dE <= 0, otherwise iff u < thr[s][min(dE, Dmax)] where u is
+ *     word (t-1) mod 4 of Philox4x32-10(counter {c + 65536 ((t-1) div 4), s,
+ *     r, inst}, key {seed, 0}) and no draw is taken when that entry is 0;
+ *   at each sweep end the state is kept as the replica's best if E < best_E.
+ * Per instance the best is the lexicographic minimum of (best_E, replica).
+ * Asynchronous on `stream`; outputs are valid once the stream has drained. */
+int uavq_anneal_batch(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
+                      const uavq_anneal_out *out, void *stream);
+
+/* Kernel timing for measurement: when enabled, uavq_anneal_batch records HIP
+ * events on its stream around the sweep-kernel launches of this plan, and
+ * uavq_plan_sweep_ms returns their elapsed time (ms) for the last call once
+ * the stream has drained.  Changes no result.  Not thread-safe per plan. */
+int uavq_plan_set_timing(uavq_plan *plan, int32_t enable);
+int uavq_plan_sweep_ms(const uavq_plan *plan, float *ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* UAVQ_H */

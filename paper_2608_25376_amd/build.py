@@ -1,0 +1,63 @@
+"""Build ``libuavq.so`` (host code + HIP kernels for gfx950) in-tree with hipcc."""
+import os
+import shutil
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libuavq.so")
+SOURCES = ["uavq_host.cpp", "uavq_kernels.hip"]
+HEADERS = ["uavq_internal.h", os.path.join("..", "..", "include", "uavq.h")]
+ARCH = os.environ.get("UAVQ_OFFLOAD_ARCH", "gfx950")
+
+
+def _hipcc():
+    h = shutil.which("hipcc")
+    if h:
+        return h
+    if os.path.exists("/opt/rocm/bin/hipcc"):
+        return "/opt/rocm/bin/hipcc"
+    raise RuntimeError("hipcc not found: the HIP library cannot be built")
+
+
+def sources():
+    return [os.path.join(CSRC, s) for s in SOURCES] + [os.path.normpath(os.path.join(CSRC, h)) for h in HEADERS]
+
+
+def stale():
+    if not os.path.exists(LIB):
+        return True
+    t = os.path.getmtime(LIB)
+    return any(os.path.getmtime(s) > t for s in sources())
+
+
+def build(force: bool = True, verbose: bool = False) -> str:
+    if not force and not stale():
+        return LIB
+    hipcc = _hipcc()
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
+    # Packed FP32 instructions stay off in all device code.
+    dev = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    objs = []
+    for s in SOURCES:
+        src = os.path.join(CSRC, s)
+        obj = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
+        if s.endswith(".hip"):
+            cmd = [hipcc, "-x", "hip"] + dev + common + ["-c", src, "-o", obj]
+        else:
+            cmd = [hipcc, "-x", "c++"] + common + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd))
+        subprocess.run(cmd, check=True)
+        objs.append(obj)
+    tmp = LIB + ".tmp"
+    subprocess.run([hipcc, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs, check=True)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(force=True, verbose="-v" in sys.argv))

@@ -1,0 +1,433 @@
+// Host side of libuavq: QUBO construction, schedule table, host energy and
+// path decoding, plan packing and the C entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "uavq_internal.h"
+
+namespace uavq {
+
+static thread_local std::string g_err;
+
+int set_error(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+static size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// floor(sqrt(v)) for v >= 0, exact for all 64-bit inputs used here.
+static int64_t isqrt64(int64_t v) {
+    int64_t r = (int64_t)std::sqrt((double)v);
+    while (r > 0 && r * r > v) r--;
+    while ((r + 1) * (r + 1) <= v) r++;
+    return r;
+}
+
+// round(scale * sqrt(q)) = floor((isqrt(4 scale^2 q) + 1) / 2); exact because
+// 4 scale^2 q is even, so scale*sqrt(q) is never a half-integer.
+static int32_t travel_cost(int32_t cols, int32_t ga, int32_t gb, int32_t scale) {
+    int64_t di = ga / cols - gb / cols, dj = ga % cols - gb % cols;
+    int64_t q = di * di + dj * dj;
+    return (int32_t)((isqrt64(4LL * scale * scale * q) + 1) >> 1);
+}
+
+static double temperature(double T0, double T1, int32_t S, int32_t s) {
+    return S <= 1 ? T0 : T0 * std::pow(T1 / T0, (double)s / (double)(S - 1));
+}
+
+static uint32_t threshold(int32_t d, double T) {
+    double v = std::floor(std::ldexp(std::exp(-(double)d / T), 32));
+    return v >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)v;
+}
+
+}  // namespace uavq
+
+using namespace uavq;
+
+extern "C" {
+
+const char *uavq_last_error(void) { return g_err.c_str(); }
+
+int32_t uavq_version(void) { return 100; }
+
+int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out) {
+    if (!g || !out) return set_error(UAVQ_EINVAL, "qubo_build: null argument");
+    *out = nullptr;
+    if (g->rows < 1 || g->cols < 1 || (int64_t)g->rows * g->cols > 65536)
+        return set_error(UAVQ_EINVAL, "qubo_build: grid %dx%d out of range", g->rows, g->cols);
+    int32_t cells = g->rows * g->cols;
+    if (g->depot < 0 || g->depot >= cells) return set_error(UAVQ_EINVAL, "qubo_build: start cell out of range");
+    if (g->nofly && g->nofly[g->depot]) return set_error(UAVQ_EINVAL, "qubo_build: start cell is no-fly");
+    int32_t scale = g->cost_scale ? g->cost_scale : 10;
+    if (scale < 1 || scale > 10000) return set_error(UAVQ_EINVAL, "qubo_build: cost_scale out of range");
+
+    uavq_qubo *q = new (std::nothrow) uavq_qubo();
+    if (!q) return set_error(UAVQ_ENOMEM, "qubo_build: out of memory");
+    q->rows = g->rows; q->cols = g->cols; q->depot = g->depot; q->scale = scale;
+    q->closed = (g->flags & UAVQ_OPEN_PATH) ? 0 : 1;
+    for (int32_t c = 0; c < cells; c++)
+        if (c != g->depot && !(g->nofly && g->nofly[c])) q->F.push_back(c);
+    int32_t m = (int32_t)q->F.size();
+    if (m < 1) { delete q; return set_error(UAVQ_EINVAL, "qubo_build: no cell to visit"); }
+    q->m = m;
+    q->N = m * m;
+    q->row_words = (m + 31) / 32;
+
+    // visit list V = [start, F...]; W over V x V
+    q->W.assign((size_t)(m + 1) * (m + 1), 0);
+    int32_t wmax = 0;
+    for (int32_t a = 0; a <= m; a++) {
+        int32_t ga = a ? q->F[a - 1] : g->depot;
+        for (int32_t b = 0; b <= m; b++) {
+            int32_t gb = b ? q->F[b - 1] : g->depot;
+            int32_t w = travel_cost(g->cols, ga, gb, scale);
+            q->W[(size_t)a * (m + 1) + b] = w;
+            wmax = std::max(wmax, w);
+        }
+    }
+    q->wmax = wmax;
+    if (wmax > 255) { delete q; return set_error(UAVQ_ETOOBIG, "qubo_build: w_max %d > 255", wmax); }
+    int32_t P = g->penalty ? g->penalty : 2 * wmax;
+    if (P <= wmax) { delete q; return set_error(UAVQ_EINVAL, "qubo_build: penalty %d <= w_max %d", P, wmax); }
+    if (P > (1 << 20)) { delete q; return set_error(UAVQ_EINVAL, "qubo_build: penalty too large"); }
+    q->P = P;
+    q->c0 = 2LL * P * m;
+    q->D.resize((size_t)m * m);
+    q->ddep.resize(m);
+    for (int32_t c = 0; c < m; c++) {
+        q->ddep[c] = (uint8_t)q->W[c + 1];
+        for (int32_t c2 = 0; c2 < m; c2++) q->D[(size_t)c * m + c2] = (uint8_t)q->W[(size_t)(c + 1) * (m + 1) + c2 + 1];
+    }
+    q->b.resize(q->N);
+    for (int32_t t = 1; t <= m; t++)
+        for (int32_t c = 0; c < m; c++) {
+            int32_t v = -2 * P;
+            if (t == 1) v += q->ddep[c];
+            if (t == m && q->closed) v += q->ddep[c];
+            q->b[(size_t)(t - 1) * m + c] = v;
+        }
+    if (g->flags & UAVQ_DENSE) {
+        if (q->N > 46340 || 2 * P + 255 > 32767) {
+            delete q;
+            return set_error(UAVQ_ETOOBIG, "qubo_build: dense J too large (N=%d, P=%d)", m * m, P);
+        }
+        try {
+            q->J.assign((size_t)q->N * q->N, 0);
+        } catch (...) {
+            delete q;
+            return set_error(UAVQ_ENOMEM, "qubo_build: dense J allocation failed");
+        }
+        // same step: 2P between different cells; same cell: 2P between
+        // different steps; adjacent steps: travel cost between the cells.
+        for (int32_t t = 0; t < m; t++)
+            for (int32_t c = 0; c < m; c++) {
+                int16_t *row = &q->J[(size_t)(t * m + c) * q->N];
+                for (int32_t c2 = 0; c2 < m; c2++)
+                    if (c2 != c) row[t * m + c2] += (int16_t)(2 * P);
+                for (int32_t t2 = 0; t2 < m; t2++)
+                    if (t2 != t) row[t2 * m + c] += (int16_t)(2 * P);
+                for (int32_t dt = -1; dt <= 1; dt += 2) {
+                    int32_t t2 = t + dt;
+                    if (t2 < 0 || t2 >= m) continue;
+                    for (int32_t c2 = 0; c2 < m; c2++) row[t2 * m + c2] += (int16_t)q->D[(size_t)c * m + c2];
+                }
+            }
+    }
+    *out = q;
+    return UAVQ_OK;
+}
+
+void uavq_qubo_free(uavq_qubo *q) { delete q; }
+
+int uavq_qubo_info(const uavq_qubo *q, uavq_qubo_info_t *info) {
+    if (!q || !info) return set_error(UAVQ_EINVAL, "qubo_info: null argument");
+    info->m = q->m;
+    info->n_vars = q->N;
+    info->P = q->P;
+    info->w_max = q->wmax;
+    info->c0 = q->c0;
+    info->closed = q->closed;
+    info->has_dense = q->J.empty() ? 0 : 1;
+    info->row_words = q->row_words;
+    info->state_words = q->m * q->row_words;
+    return UAVQ_OK;
+}
+
+int uavq_qubo_free_cells(const uavq_qubo *q, int32_t *F) {
+    if (!q || !F) return set_error(UAVQ_EINVAL, "qubo_free_cells: null argument");
+    std::memcpy(F, q->F.data(), sizeof(int32_t) * q->F.size());
+    return UAVQ_OK;
+}
+
+int uavq_qubo_costs(const uavq_qubo *q, int32_t *W) {
+    if (!q || !W) return set_error(UAVQ_EINVAL, "qubo_costs: null argument");
+    std::memcpy(W, q->W.data(), sizeof(int32_t) * q->W.size());
+    return UAVQ_OK;
+}
+
+int uavq_qubo_export(const uavq_qubo *q, int32_t *b, int32_t *J) {
+    if (!q || !b) return set_error(UAVQ_EINVAL, "qubo_export: null argument");
+    std::memcpy(b, q->b.data(), sizeof(int32_t) * q->b.size());
+    if (J) {
+        if (q->J.empty()) return set_error(UAVQ_EINVAL, "qubo_export: built without UAVQ_DENSE");
+        for (size_t i = 0; i < q->J.size(); i++) J[i] = q->J[i];
+    }
+    return UAVQ_OK;
+}
+
+// E = c0 + sum_k b_k x_k + P sum_t R_t (R_t - 1) + P sum_c C_c (C_c - 1)
+//     + sum_{t=1}^{m-1} sum_{c,c'} D[c][c'] x_{t,c} x_{t+1,c'}
+// (R_t, C_c the step and cell occupation counts): the pair sum of the
+// expanded form grouped by the three kinds of coupling.
+int uavq_energy_eval(const uavq_qubo *q, const uint32_t *x, int64_t n, int64_t *E) {
+    if (!q || (n > 0 && (!x || !E)) || n < 0) return set_error(UAVQ_EINVAL, "energy_eval: bad argument");
+    const int32_t m = q->m, W = q->row_words, sw = m * W;
+    std::vector<int32_t> colcnt(m);
+    std::vector<int32_t> ones, prev;
+    for (int64_t i = 0; i < n; i++) {
+        const uint32_t *s = x + i * sw;
+        int64_t e = q->c0;
+        std::fill(colcnt.begin(), colcnt.end(), 0);
+        prev.clear();
+        for (int32_t t = 1; t <= m; t++) {
+            ones.clear();
+            for (int32_t c = 0; c < m; c++)
+                if ((s[(size_t)(t - 1) * W + (c >> 5)] >> (c & 31)) & 1u) ones.push_back(c);
+            int64_t R = (int64_t)ones.size();
+            e += (int64_t)q->P * R * (R - 1);
+            for (int32_t c : ones) {
+                e += q->b[(size_t)(t - 1) * m + c];
+                colcnt[c]++;
+                for (int32_t cp : prev) e += q->D[(size_t)cp * m + c];
+            }
+            prev.swap(ones);
+        }
+        for (int32_t c = 0; c < m; c++) e += (int64_t)q->P * colcnt[c] * (colcnt[c] - 1);
+        E[i] = e;
+    }
+    return UAVQ_OK;
+}
+
+int uavq_decode_path(const uavq_qubo *q, const uint32_t *x, int32_t *path, int64_t *cost) {
+    if (!q || !x || !path || !cost) return set_error(UAVQ_EINVAL, "decode_path: null argument");
+    const int32_t m = q->m, W = q->row_words;
+    std::vector<int32_t> order(m, -1);
+    std::vector<char> used(m, 0);
+    for (int32_t t = 1; t <= m; t++) {
+        for (int32_t c = 0; c < m; c++) {
+            if (!((x[(size_t)(t - 1) * W + (c >> 5)] >> (c & 31)) & 1u)) continue;
+            if (order[t - 1] >= 0 || used[c])
+                return set_error(UAVQ_EINFEASIBLE, "decode_path: step %d or cell %d occupied twice", t, c);
+            order[t - 1] = c;
+            used[c] = 1;
+        }
+        if (order[t - 1] < 0) return set_error(UAVQ_EINFEASIBLE, "decode_path: step %d empty", t);
+    }
+    int64_t total = q->ddep[order[0]];
+    path[0] = q->depot;
+    for (int32_t t = 0; t < m; t++) {
+        path[t + 1] = q->F[order[t]];
+        if (t > 0) total += q->D[(size_t)order[t - 1] * m + order[t]];
+    }
+    if (q->closed) {
+        total += q->ddep[order[m - 1]];
+        path[m + 1] = q->depot;
+    } else {
+        path[m + 1] = -1;
+    }
+    *cost = total;
+    return UAVQ_OK;
+}
+
+int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr) {
+    if (!Dmax || S < 1 || !(T1 > 0.0) || !(T1 <= T0) || !std::isfinite(T0) || T0 > 1e7)
+        return set_error(UAVQ_EINVAL, "schedule: need S >= 1 and 0 < T1 <= T0 (finite)");
+    int32_t d = 1;
+    while (threshold(d, T0) != 0) d++;
+    *Dmax = d;
+    if (thr) {
+        const int32_t w = d + 1;
+        for (int32_t s = 0; s < S; s++) {
+            double T = temperature(T0, T1, S, s);
+            uint32_t *row = thr + (size_t)s * w;
+            row[0] = 0xFFFFFFFFu;
+            for (int32_t k = 1; k <= d; k++) row[k] = threshold(k, T);
+        }
+    }
+    return UAVQ_OK;
+}
+
+// ------------------------------------------------------------------ plans --
+
+static int default_waves_per_block(int chunks) {
+    (void)chunks;
+    return 4;
+}
+
+int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *inst_ids,
+                     const uavq_anneal_params *p, uavq_plan **out) {
+    if (!out || !p || n_inst < 0 || (n_inst > 0 && (!q || !inst_ids)))
+        return set_error(UAVQ_EINVAL, "plan_create: bad argument");
+    *out = nullptr;
+    if (p->replicas < 1 || p->replicas > (1 << 20)) return set_error(UAVQ_EINVAL, "plan_create: replicas out of range");
+    if (p->sweeps < 1) return set_error(UAVQ_EINVAL, "plan_create: sweeps must be >= 1");
+    if (p->waves_per_block < 0 || p->waves_per_block > 16)
+        return set_error(UAVQ_EINVAL, "plan_create: waves_per_block must be 0..16");
+    const bool dense = (p->flags & UAVQ_KERNEL_DENSE) != 0;
+    for (int32_t i = 0; i < n_inst; i++) {
+        if (!q[i]) return set_error(UAVQ_EINVAL, "plan_create: null qubo %d", i);
+        if (dense && q[i]->J.empty()) return set_error(UAVQ_EINVAL, "plan_create: dense kernel needs UAVQ_DENSE (instance %d)", i);
+        if (!dense && q[i]->m > kMaxM)
+            return set_error(UAVQ_ETOOBIG, "plan_create: m = %d exceeds the factored kernel's %d", q[i]->m, kMaxM);
+    }
+    int32_t Dmax = 0;
+    int rc = uavq_schedule(p->T0, p->T1, p->sweeps, &Dmax, nullptr);
+    if (rc) return rc;
+
+    uavq_plan *pl = new (std::nothrow) uavq_plan();
+    if (!pl) return set_error(UAVQ_ENOMEM, "plan_create: out of memory");
+    pl->p = *p;
+    pl->n_inst = n_inst;
+    pl->S = p->sweeps;
+    pl->Dmax = Dmax;
+    pl->dense = dense ? 1 : 0;
+    const int32_t S = p->sweeps, R = p->replicas;
+
+    std::vector<uint32_t> thr((size_t)S * (Dmax + 1));
+    uavq_schedule(p->T0, p->T1, S, &Dmax, thr.data());
+    std::vector<int32_t> dcut(S);
+    for (int32_t s = 0; s < S; s++) {
+        int32_t d = 1;
+        while (d < Dmax && thr[(size_t)s * (Dmax + 1) + d] != 0) d++;
+        dcut[s] = d;
+    }
+
+    // replica and state layout, per-instance descriptors
+    pl->rep_offset.assign(n_inst + 1, 0);
+    pl->state_offset.assign(n_inst + 1, 0);
+    pl->inst_state_off.assign(n_inst + 1, 0);
+    pl->desc.resize(n_inst);
+    pl->max_m = 0;
+    for (int32_t i = 0; i < n_inst; i++) {
+        const uavq_qubo *qi = q[i];
+        int32_t sw = qi->m * qi->row_words;
+        pl->rep_offset[i + 1] = pl->rep_offset[i] + R;
+        pl->state_offset[i + 1] = pl->state_offset[i] + (int64_t)R * sw;
+        pl->inst_state_off[i + 1] = pl->inst_state_off[i] + sw;
+        pl->max_m = std::max(pl->max_m, qi->m);
+    }
+    pl->total_rep = pl->rep_offset[n_inst];
+    pl->total_state_words = pl->state_offset[n_inst];
+
+    // blob: thr | dcut | desc | items | inst_state_off | per-instance data
+    size_t off = 0;
+    pl->thr_off = off;          off = align_up(off + thr.size() * 4, 256);
+    pl->dcut_off = off;         off = align_up(off + dcut.size() * 4, 256);
+    pl->desc_off = off;         off = align_up(off + sizeof(InstDesc) * (size_t)std::max(n_inst, 1), 256);
+
+    // work items: groups of waves_per_block replicas, ordered by chunk class
+    // and, inside a class, by decreasing m (largest first).
+    std::vector<int32_t> order(n_inst);
+    for (int32_t i = 0; i < n_inst; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return q[a]->m > q[b]->m; });
+    pl->items.clear();
+    for (int c = 0; c <= kMaxChunks + 1; c++) pl->class_begin[c] = 0;
+    for (int cls = 1; cls <= kMaxChunks; cls++) {
+        int wpb = p->waves_per_block ? p->waves_per_block : default_waves_per_block(cls);
+        pl->waves_per_block[cls] = wpb;
+        pl->class_begin[cls] = (int32_t)pl->items.size();
+        for (int32_t i : order) {
+            int32_t chunks = dense ? 1 : (q[i]->m + 63) / 64;
+            if (chunks != cls) continue;
+            for (int32_t r0 = 0; r0 < R; r0 += wpb) pl->items.push_back({i, r0, std::min(wpb, R - r0), 0});
+        }
+    }
+    pl->waves_per_block[0] = pl->waves_per_block[1];
+    pl->class_begin[kMaxChunks + 1] = (int32_t)pl->items.size();
+    pl->items_off = off;        off = align_up(off + sizeof(WorkItem) * std::max<size_t>(pl->items.size(), 1), 256);
+    pl->inst_state_off_off = off; off = align_up(off + 8 * (size_t)(n_inst + 1), 256);
+
+    for (int32_t i = 0; i < n_inst; i++) {
+        const uavq_qubo *qi = q[i];
+        InstDesc &d = pl->desc[i];
+        d.m = qi->m; d.P = qi->P; d.closed = qi->closed; d.row_words = qi->row_words;
+        d.state_words = qi->m * qi->row_words;
+        d.nrep = R;
+        d.c0 = qi->c0;
+        d.d_off = (int64_t)off;     off = align_up(off + qi->D.size(), 16);
+        d.ddep_off = (int64_t)off;  off = align_up(off + qi->ddep.size(), 256);
+        if (dense) {
+            d.J_off = (int64_t)off; off = align_up(off + qi->J.size() * 2, 256);
+            d.b_off = (int64_t)off; off = align_up(off + qi->b.size() * 4, 256);
+        } else {
+            d.J_off = -1;
+            d.b_off = -1;
+        }
+        d.rep_base = pl->rep_offset[i];
+        d.state_off = pl->state_offset[i];
+        d.inst_id = inst_ids[i];
+        d.chunks = (qi->m + 63) / 64;
+    }
+    pl->blob_bytes = align_up(off, 256);
+    try {
+        pl->blob.assign(pl->blob_bytes, 0);
+    } catch (...) {
+        delete pl;
+        return set_error(UAVQ_ENOMEM, "plan_create: out of host memory");
+    }
+    uint8_t *B = pl->blob.data();
+    std::memcpy(B + pl->thr_off, thr.data(), thr.size() * 4);
+    std::memcpy(B + pl->dcut_off, dcut.data(), dcut.size() * 4);
+    if (n_inst) std::memcpy(B + pl->desc_off, pl->desc.data(), sizeof(InstDesc) * n_inst);
+    if (!pl->items.empty()) std::memcpy(B + pl->items_off, pl->items.data(), sizeof(WorkItem) * pl->items.size());
+    std::memcpy(B + pl->inst_state_off_off, pl->inst_state_off.data(), 8 * (size_t)(n_inst + 1));
+    for (int32_t i = 0; i < n_inst; i++) {
+        const uavq_qubo *qi = q[i];
+        const InstDesc &d = pl->desc[i];
+        std::memcpy(B + d.d_off, qi->D.data(), qi->D.size());
+        std::memcpy(B + d.ddep_off, qi->ddep.data(), qi->ddep.size());
+        if (dense) {
+            std::memcpy(B + d.J_off, qi->J.data(), qi->J.size() * 2);
+            std::memcpy(B + d.b_off, qi->b.data(), qi->b.size() * 4);
+        }
+    }
+    pl->e_init_off = pl->blob_bytes;
+    pl->ws_bytes = align_up(pl->e_init_off + 8 * (size_t)std::max<int64_t>(pl->total_rep, 1), 256);
+    *out = pl;
+    return UAVQ_OK;
+}
+
+void uavq_plan_free(uavq_plan *plan) {
+    if (!plan) return;
+    plan_destroy_events(plan);
+    delete plan;
+}
+
+int uavq_plan_info(const uavq_plan *pl, uavq_plan_info_t *info) {
+    if (!pl || !info) return set_error(UAVQ_EINVAL, "plan_info: null argument");
+    info->ws_bytes = pl->ws_bytes;
+    info->total_replicas = pl->total_rep;
+    info->total_state_words = pl->total_state_words;
+    info->n_inst = pl->n_inst;
+    info->Dmax = pl->Dmax;
+    return UAVQ_OK;
+}
+
+int uavq_plan_layout(const uavq_plan *pl, int64_t *rep_offset, int64_t *state_offset) {
+    if (!pl) return set_error(UAVQ_EINVAL, "plan_layout: null plan");
+    if (rep_offset) std::memcpy(rep_offset, pl->rep_offset.data(), 8 * (size_t)(pl->n_inst + 1));
+    if (state_offset) std::memcpy(state_offset, pl->state_offset.data(), 8 * (size_t)(pl->n_inst + 1));
+    return UAVQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,109 @@
+// Internal structures shared by the host code and the HIP kernels of libuavq.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/uavq.h"
+
+namespace uavq {
+
+// Largest number of 64-column chunks a replica row may span in the factored
+// kernel (m <= 64 * kMaxChunks).
+constexpr int kMaxChunks = 3;
+constexpr int kMaxM = 64 * kMaxChunks;
+
+int set_error(int code, const char *fmt, ...);
+
+// Device-side descriptor of one instance inside a plan's workspace.
+struct InstDesc {
+    int32_t m, P, closed, row_words;
+    int32_t state_words, nrep;
+    int64_t c0;
+    int64_t d_off;      // byte offset of D (m*m uint8, row-major)
+    int64_t ddep_off;   // byte offset of the start-cell costs (m uint8)
+    int64_t J_off;      // byte offset of the dense J (N*N int16) or -1
+    int64_t b_off;      // byte offset of b (N int32) or -1
+    int64_t rep_base;   // global index of replica 0
+    int64_t state_off;  // word offset of replica 0's state
+    uint32_t inst_id;
+    int32_t chunks;     // ceil(m / 64)
+};
+
+// One workgroup's share: replicas rep0 .. rep0+nrep-1 of instance inst.
+struct WorkItem {
+    int32_t inst, rep0, nrep, pad;
+};
+
+// Kernel argument block (passed by value).
+struct KArgs {
+    const uint8_t *ws;          // workspace base
+    const InstDesc *desc;
+    const WorkItem *items;
+    int32_t n_items;
+    int32_t item_base;          // first item of this launch
+    const uint32_t *thr;        // S x (Dmax+1)
+    const int32_t *dcut;        // S: least d with thr[s][d] == 0
+    int32_t S, Dmax;
+    uint32_t seed;
+    int32_t n_inst;
+    int64_t total_rep;
+    // inputs
+    const uint32_t *init_states;
+    const uint8_t *seeded;
+    const int32_t *start_sweep;
+    // working / outputs
+    uint32_t *states;           // current state (final on exit)
+    int64_t *E_init;            // workspace: energy of the initial state
+    int64_t *final_E, *best_E;
+    int32_t *best_sweep;
+    uint32_t *best_states;
+    uint64_t *accepts, *draws;
+    int64_t *inst_best_E;
+    int32_t *inst_best_replica, *inst_best_sweep;
+    uint32_t *inst_best_state;
+    int64_t *inst_state_off;    // per instance: word offset of its best state in inst_best_state
+};
+
+}  // namespace uavq
+
+struct uavq_qubo {
+    int32_t rows, cols, depot, scale;
+    int32_t m, N, P, wmax, closed, row_words;
+    int64_t c0;
+    std::vector<int32_t> F;      // m grid indices
+    std::vector<int32_t> W;      // (m+1)^2 costs over [start, F...]
+    std::vector<uint8_t> D;      // m*m costs between free cells
+    std::vector<uint8_t> ddep;   // m costs start -> free cell
+    std::vector<int32_t> b;      // N linear terms
+    std::vector<int16_t> J;      // N*N dense couplings (optional)
+};
+
+struct uavq_plan {
+    uavq_anneal_params p;
+    int32_t n_inst, S, Dmax;
+    std::vector<uint8_t> blob;            // static data, uploaded verbatim at offset 0
+    size_t thr_off, dcut_off, desc_off, items_off, inst_state_off_off;
+    size_t blob_bytes;                    // aligned size of blob
+    size_t e_init_off;                    // int64 per replica
+    size_t ws_bytes;
+    std::vector<uavq::InstDesc> desc;
+    std::vector<uavq::WorkItem> items;    // ordered by chunk class, then LPT
+    int32_t class_begin[uavq::kMaxChunks + 2];   // items of chunk class j: [class_begin[j], class_begin[j+1])
+    int32_t waves_per_block[uavq::kMaxChunks + 1];
+    int64_t total_rep, total_state_words;
+    std::vector<int64_t> rep_offset, state_offset, inst_state_off;
+    int32_t max_m, dense;
+    int32_t timing = 0;                   // record events around the sweep launches
+    void *ev[2 * (uavq::kMaxChunks + 1)] = {};
+};
+
+extern "C" void plan_destroy_events(uavq_plan *pl);
+
+// Kernel launchers (uavq_kernels.hip).
+namespace uavq {
+int launch_anneal(const uavq_plan *plan, const KArgs &a, void *stream, int64_t *check_E);
+int launch_energy(const uavq_qubo *q, const uint32_t *d_x, int64_t n, int64_t *d_E, void *d_ws,
+                  size_t ws_bytes, void *stream);
+size_t energy_ws_bytes(const uavq_qubo *q);
+}  // namespace uavq

@@ -1,0 +1,335 @@
+"""Thin Python binding over ``libuavq.so`` (the C ABI in ``include/uavq.h``).
+
+Argument marshalling only: every step of the annealing path runs in the
+library's HIP kernels.  Device buffers are torch tensors (PyTorch provides
+device memory and streams, nothing else).  The library must have been built
+(``paper_2608_25376_amd/build.py``); a missing library is an error.
+"""
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libuavq.so")
+
+OPEN_PATH = 0x1
+DENSE = 0x2
+KERNEL_DENSE = 0x1
+
+OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
+
+
+class UavqError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"uavq error {code}: {msg}")
+        self.code = code
+
+
+class _Grid(C.Structure):
+    _fields_ = [("rows", C.c_int32), ("cols", C.c_int32), ("depot", C.c_int32),
+                ("nofly", C.POINTER(C.c_uint8)), ("cost_scale", C.c_int32), ("penalty", C.c_int32),
+                ("flags", C.c_uint32)]
+
+
+class _QuboInfo(C.Structure):
+    _fields_ = [("m", C.c_int32), ("n_vars", C.c_int32), ("P", C.c_int32), ("w_max", C.c_int32),
+                ("c0", C.c_int64), ("closed", C.c_int32), ("has_dense", C.c_int32), ("row_words", C.c_int32),
+                ("state_words", C.c_int32)]
+
+
+class _Params(C.Structure):
+    _fields_ = [("replicas", C.c_int32), ("sweeps", C.c_int32), ("T0", C.c_double), ("T1", C.c_double),
+                ("seed", C.c_uint32), ("flags", C.c_uint32), ("waves_per_block", C.c_int32)]
+
+
+class _PlanInfo(C.Structure):
+    _fields_ = [("ws_bytes", C.c_size_t), ("total_replicas", C.c_int64), ("total_state_words", C.c_int64),
+                ("n_inst", C.c_int32), ("Dmax", C.c_int32)]
+
+
+class _Init(C.Structure):
+    _fields_ = [("states", C.c_void_p), ("seeded", C.c_void_p), ("start_sweep", C.c_void_p)]
+
+
+class _Out(C.Structure):
+    _fields_ = [(n, C.c_void_p) for n in (
+        "final_states", "final_E", "best_E", "best_sweep", "best_states", "accepts", "draws", "inst_best_E",
+        "inst_best_replica", "inst_best_sweep", "inst_best_state", "check_E")]
+
+
+EXPORTS = [
+    "uavq_last_error", "uavq_version", "uavq_qubo_build", "uavq_qubo_free", "uavq_qubo_info",
+    "uavq_qubo_free_cells", "uavq_qubo_costs", "uavq_qubo_export", "uavq_energy_eval",
+    "uavq_energy_workspace_bytes", "uavq_energy_eval_dev", "uavq_decode_path", "uavq_schedule",
+    "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_layout", "uavq_plan_upload",
+    "uavq_anneal_batch", "uavq_plan_set_timing", "uavq_plan_sweep_ms",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libuavq.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: run paper_2608_25376_amd/build.py (or __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        P = C.POINTER
+        vp = C.c_void_p
+        L.uavq_last_error.restype = C.c_char_p
+        L.uavq_version.restype = C.c_int32
+        L.uavq_qubo_build.argtypes = [P(_Grid), P(vp)]
+        L.uavq_qubo_free.argtypes = [vp]
+        L.uavq_qubo_free.restype = None
+        L.uavq_qubo_info.argtypes = [vp, P(_QuboInfo)]
+        L.uavq_qubo_free_cells.argtypes = [vp, P(C.c_int32)]
+        L.uavq_qubo_costs.argtypes = [vp, P(C.c_int32)]
+        L.uavq_qubo_export.argtypes = [vp, P(C.c_int32), P(C.c_int32)]
+        L.uavq_energy_eval.argtypes = [vp, P(C.c_uint32), C.c_int64, P(C.c_int64)]
+        L.uavq_energy_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
+        L.uavq_energy_eval_dev.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]
+        L.uavq_decode_path.argtypes = [vp, P(C.c_uint32), P(C.c_int32), P(C.c_int64)]
+        L.uavq_schedule.argtypes = [C.c_double, C.c_double, C.c_int32, P(C.c_int32), P(C.c_uint32)]
+        L.uavq_plan_create.argtypes = [P(vp), C.c_int32, P(C.c_uint32), P(_Params), P(vp)]
+        L.uavq_plan_free.argtypes = [vp]
+        L.uavq_plan_free.restype = None
+        L.uavq_plan_info.argtypes = [vp, P(_PlanInfo)]
+        L.uavq_plan_layout.argtypes = [vp, P(C.c_int64), P(C.c_int64)]
+        L.uavq_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
+        L.uavq_anneal_batch.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), vp]
+        L.uavq_plan_set_timing.argtypes = [vp, C.c_int32]
+        L.uavq_plan_sweep_ms.argtypes = [vp, P(C.c_float)]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise UavqError(rc, lib().uavq_last_error().decode())
+
+
+def _np_ptr(a, ct):
+    return a.ctypes.data_as(C.POINTER(ct))
+
+
+def _dptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream_handle(stream):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+# ------------------------------------------------------------------ QUBO ----
+class Qubo:
+    """Handle returned by qubo_build (library-owned, immutable)."""
+
+    def __init__(self, handle):
+        self._h = C.c_void_p(handle)
+        info = _QuboInfo()
+        _check(lib().uavq_qubo_info(self._h, C.byref(info)))
+        self.m, self.n_vars, self.P, self.w_max = info.m, info.n_vars, info.P, info.w_max
+        self.c0, self.closed, self.has_dense = info.c0, bool(info.closed), bool(info.has_dense)
+        self.row_words, self.state_words = info.row_words, info.state_words
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.uavq_qubo_free(self._h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def free_cells(self):
+        F = np.zeros(self.m, np.int32)
+        _check(lib().uavq_qubo_free_cells(self._h, _np_ptr(F, C.c_int32)))
+        return F
+
+    def costs(self):
+        W = np.zeros((self.m + 1, self.m + 1), np.int32)
+        _check(lib().uavq_qubo_costs(self._h, _np_ptr(W, C.c_int32)))
+        return W
+
+    def export(self, dense=False):
+        b = np.zeros(self.n_vars, np.int32)
+        J = np.zeros((self.n_vars, self.n_vars), np.int32) if dense else None
+        _check(lib().uavq_qubo_export(self._h, _np_ptr(b, C.c_int32), None if J is None else _np_ptr(J, C.c_int32)))
+        return b, J
+
+
+def qubo_build(rows, cols, nofly=None, depot=0, cost_scale=10, penalty=0, closed=True, dense=False) -> Qubo:
+    g = _Grid()
+    g.rows, g.cols, g.depot, g.cost_scale, g.penalty = rows, cols, depot, cost_scale, penalty
+    g.flags = (0 if closed else OPEN_PATH) | (DENSE if dense else 0)
+    nf = None
+    if nofly is not None:
+        nf = np.ascontiguousarray(nofly, dtype=np.uint8).reshape(-1)
+        if nf.size != rows * cols:
+            raise ValueError("nofly must have rows*cols entries")
+        g.nofly = _np_ptr(nf, C.c_uint8)
+    h = C.c_void_p()
+    _check(lib().uavq_qubo_build(C.byref(g), C.byref(h)))
+    return Qubo(h.value)
+
+
+# ------------------------------------------------------ state packing ------
+def pack_states(x, m):
+    """uint8 states [..., m*m] (t-major) -> packed uint32 [..., m*ceil(m/32)]."""
+    x = np.asarray(x, np.uint8)
+    lead = x.shape[:-1]
+    W = (m + 31) // 32
+    X = x.reshape(-1, m, m)
+    pad = np.zeros((X.shape[0], m, W * 32), np.uint8)
+    pad[:, :, :m] = X
+    words = np.packbits(pad.reshape(X.shape[0], m, W, 32)[..., ::-1], axis=-1).view(">u4").astype(np.uint32)
+    return words.reshape(lead + (m * W,))
+
+
+def unpack_states(p, m):
+    """packed uint32 [..., m*ceil(m/32)] -> uint8 [..., m*m]."""
+    p = np.asarray(p, np.uint32)
+    lead = p.shape[:-1]
+    W = (m + 31) // 32
+    P = p.reshape(-1, m, W).astype(">u4").view(np.uint8).reshape(-1, m, W, 4)
+    bits = np.unpackbits(P, axis=-1).reshape(-1, m, W, 32)[..., ::-1].reshape(-1, m, W * 32)[:, :, :m]
+    return np.ascontiguousarray(bits).reshape(lead + (m * m,))
+
+
+# --------------------------------------------------------------- energy -----
+def energy_eval(q: Qubo, x_packed) -> np.ndarray:
+    x = np.ascontiguousarray(x_packed, dtype=np.uint32).reshape(-1, q.state_words)
+    E = np.zeros(x.shape[0], np.int64)
+    _check(lib().uavq_energy_eval(q.handle, _np_ptr(x, C.c_uint32), x.shape[0], _np_ptr(E, C.c_int64)))
+    return E
+
+
+def energy_eval_dev(q: Qubo, d_states, d_E=None, stream=None):
+    import torch
+    n = d_states.numel() // q.state_words
+    if d_E is None:
+        d_E = torch.empty(n, dtype=torch.int64, device=d_states.device)
+    nb = C.c_size_t()
+    _check(lib().uavq_energy_workspace_bytes(q.handle, C.byref(nb)))
+    ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=d_states.device)
+    _check(lib().uavq_energy_eval_dev(q.handle, _dptr(d_states), n, _dptr(d_E), _dptr(ws), nb.value,
+                                      _stream_handle(stream)))
+    return d_E
+
+
+def decode_path(q: Qubo, x_packed):
+    x = np.ascontiguousarray(x_packed, dtype=np.uint32).reshape(-1)
+    path = np.zeros(q.m + 2, np.int32)
+    cost = C.c_int64()
+    rc = lib().uavq_decode_path(q.handle, _np_ptr(x, C.c_uint32), _np_ptr(path, C.c_int32), C.byref(cost))
+    if rc == EINFEASIBLE:
+        return None, None
+    _check(rc)
+    return path, int(cost.value)
+
+
+def schedule(T0, T1, S, table=True):
+    dmax = C.c_int32()
+    _check(lib().uavq_schedule(T0, T1, S, C.byref(dmax), None))
+    if not table:
+        return dmax.value, None
+    thr = np.zeros((S, dmax.value + 1), np.uint32)
+    _check(lib().uavq_schedule(T0, T1, S, C.byref(dmax), _np_ptr(thr, C.c_uint32)))
+    return dmax.value, thr
+
+
+# ------------------------------------------------------------ annealing -----
+@dataclass
+class AnnealResult:
+    final_states: object
+    final_E: object
+    best_E: object
+    best_sweep: object
+    best_states: object
+    accepts: object
+    draws: object
+    inst_best_E: object
+    inst_best_replica: object
+    inst_best_sweep: object
+    inst_best_state: object
+
+
+class Plan:
+    """uavq_plan_create + workspace; call ``upload`` once, then ``anneal``."""
+
+    def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
+                 T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0):
+        self.qubos = list(qubos)
+        n = len(self.qubos)
+        arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in self.qubos])
+        ids = np.ascontiguousarray(inst_ids, dtype=np.uint32)
+        assert ids.size == n
+        p = _Params(replicas, sweeps, T0, T1, seed, KERNEL_DENSE if dense else 0, waves_per_block)
+        h = C.c_void_p()
+        _check(lib().uavq_plan_create(arr, n, _np_ptr(ids, C.c_uint32), C.byref(p), C.byref(h)))
+        self._h = h
+        info = _PlanInfo()
+        _check(lib().uavq_plan_info(self._h, C.byref(info)))
+        self.ws_bytes, self.total_replicas = info.ws_bytes, info.total_replicas
+        self.total_state_words, self.n_inst, self.Dmax = info.total_state_words, info.n_inst, info.Dmax
+        self.rep_offset = np.zeros(n + 1, np.int64)
+        self.state_offset = np.zeros(n + 1, np.int64)
+        _check(lib().uavq_plan_layout(self._h, _np_ptr(self.rep_offset, C.c_int64),
+                                      _np_ptr(self.state_offset, C.c_int64)))
+        self.replicas, self.sweeps = replicas, sweeps
+        self.ws = None
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.uavq_plan_free(self._h)
+            self._h = None
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        _check(lib().uavq_plan_upload(self._h, _dptr(self.ws), self.ws_bytes, _stream_handle(stream)))
+        return self.ws
+
+    def set_timing(self, enable=True):
+        _check(lib().uavq_plan_set_timing(self._h, 1 if enable else 0))
+
+    def sweep_ms(self):
+        """Elapsed ms of the sweep kernels of the last anneal (HIP events on its stream)."""
+        v = C.c_float()
+        _check(lib().uavq_plan_sweep_ms(self._h, C.byref(v)))
+        return float(v.value)
+
+    def alloc_outputs(self, device="cuda"):
+        import torch
+        R, W = self.total_replicas, self.total_state_words
+        inst_words = int(sum(q.state_words for q in self.qubos))
+        z = lambda n, dt: torch.zeros(max(n, 1), dtype=dt, device=device)
+        return AnnealResult(
+            final_states=z(W, torch.int32), final_E=z(R, torch.int64), best_E=z(R, torch.int64),
+            best_sweep=z(R, torch.int32), best_states=z(W, torch.int32), accepts=z(R, torch.int64),
+            draws=z(R, torch.int64), inst_best_E=z(self.n_inst, torch.int64),
+            inst_best_replica=z(self.n_inst, torch.int32), inst_best_sweep=z(self.n_inst, torch.int32),
+            inst_best_state=z(inst_words, torch.int32))
+
+    def anneal(self, out: Optional[AnnealResult] = None, init_states=None, seeded=None, start_sweep=None,
+               check_E=None, stream=None) -> AnnealResult:
+        """anneal_batch on this plan's workspace (asynchronous on ``stream``)."""
+        if self.ws is None:
+            raise RuntimeError("Plan.upload() must precede anneal()")
+        if out is None:
+            out = self.alloc_outputs(self.ws.device)
+        init = _Init(_dptr(init_states), _dptr(seeded), _dptr(start_sweep))
+        o = _Out(*[_dptr(getattr(out, f)) if f != "check_E" else _dptr(check_E) for f, _ in _Out._fields_])
+        _check(lib().uavq_anneal_batch(self._h, _dptr(self.ws), self.ws_bytes, C.byref(init), C.byref(o),
+                                       _stream_handle(stream)))
+        return out
+
+
+def anneal_batch(plan: Plan, **kw) -> AnnealResult:
+    return plan.anneal(**kw)

@@ -1,0 +1,136 @@
+"""CPU tests of the C ABI: the library loads, exports every declared entry
+point, and its host-side pieces (QUBO build, schedule table, energy, path
+decoding, validation) agree with the oracle.  No GPU call is made here."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2608_25376_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def U():
+    from paper_2608_25376_amd import build as B
+    B.build(force=False)
+    from paper_2608_25376_amd import uavq
+    uavq.lib()
+    return uavq
+
+
+def test_exports_every_declared_symbol(U):
+    hdrs = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+    declared = set()
+    for h in hdrs:
+        txt = open(h).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        declared |= set(re.findall(r"\b(uavq_[a-z_0-9]+)\s*\(", txt))
+    assert declared, "no declarations found"
+    L = U.lib()
+    for name in sorted(declared):
+        assert hasattr(L, name), name
+    assert set(U.EXPORTS) == declared
+    assert L.uavq_version() >= 100
+
+
+@pytest.mark.parametrize("rows,cols,dens,closed", [(2, 2, 0.0, True), (3, 3, 0.0, True), (5, 5, 0.2, False),
+                                                   (8, 8, 0.1, True), (4, 7, 0.1, True)])
+def test_qubo_build_matches_oracle(U, oracle_lib, rows, cols, dens, closed):
+    g = inputs.grid(rows, cols, dens, seed=3, inst=rows * 10 + cols)
+    q = U.qubo_build(rows, cols, nofly=g.nofly, closed=closed, dense=True)
+    o = oracle_lib.OracleQubo(rows, cols, nofly=g.nofly, closed=closed)
+    assert q.m == o.m and q.n_vars == o.N
+    assert (q.P, q.w_max, q.c0, q.closed) == (o.P, o.wmax, o.c0, closed)
+    assert (q.free_cells() == o.F).all()
+    assert (q.costs() == o.W).all()
+    b, J = q.export(dense=True)
+    assert (b == o.b).all()
+    assert (J == o.J).all()
+
+
+def test_schedule_table_equals_oracle(U, oracle_lib):
+    for T0, T1, S in [(100.0, 0.5, 1000), (200.0, 0.5, 2000), (50.0, 50.0, 7), (3.0, 0.01, 1)]:
+        d1, t1 = U.schedule(T0, T1, S)
+        d2, t2 = oracle_lib.thresholds(T0, T1, S)
+        assert d1 == d2
+        assert t1.tobytes() == t2.tobytes()
+
+
+def test_pack_unpack_roundtrip(U):
+    rng = np.random.default_rng(0)
+    for m in (1, 5, 31, 32, 33, 54, 64, 65, 143):
+        x = (rng.random((3, m * m)) < 0.3).astype(np.uint8)
+        p = U.pack_states(x, m)
+        assert p.shape == (3, m * ((m + 31) // 32))
+        assert (U.unpack_states(p, m) == x).all()
+        # bit (c & 31) of word (t-1)*W + (c >> 5)
+        W = (m + 31) // 32
+        t, c = m - 1, m - 1
+        assert ((p[0, (t) * W + (c >> 5)] >> (c & 31)) & 1) == x[0, t * m + c]
+
+
+def test_energy_eval_and_decode_match_oracle(U, oracle_lib):
+    for side, dens, closed in [(3, 0.0, True), (6, 0.15, True), (7, 0.1, False)]:
+        g = inputs.grid(side, side, dens, seed=9, inst=side)
+        q = U.qubo_build(side, side, nofly=g.nofly, closed=closed)
+        o = oracle_lib.OracleQubo(side, side, nofly=g.nofly, closed=closed)
+        rng = np.random.default_rng(side)
+        xs = (rng.random((20, o.N)) < rng.random((20, 1)) * 0.6).astype(np.uint8)
+        perms = []
+        for _ in range(5):
+            X = np.zeros((o.m, o.m), np.uint8)
+            X[np.arange(o.m), rng.permutation(o.m)] = 1
+            perms.append(X.reshape(-1))
+        xs = np.concatenate([xs, np.array(perms)])
+        E = U.energy_eval(q, U.pack_states(xs, o.m))
+        assert [int(e) for e in E] == [o.energy(x) for x in xs]
+        for x in perms:
+            path, cost = U.decode_path(q, U.pack_states(x, o.m))
+            ref = o.decode(x)
+            assert list(path[: len(ref)]) == ref
+            assert cost == o.path_cost(ref) == o.energy(x)
+        path, cost = U.decode_path(q, U.pack_states(xs[0] * 0, o.m))
+        assert path is None
+
+
+def test_validation_errors(U):
+    with pytest.raises(U.UavqError) as e:
+        U.qubo_build(1, 1)                       # no cell to visit
+    assert e.value.code == U.EINVAL
+    nf = np.zeros(4, np.uint8)
+    nf[0] = 1
+    with pytest.raises(U.UavqError):
+        U.qubo_build(2, 2, nofly=nf)             # start cell no-fly
+    with pytest.raises(U.UavqError):
+        U.qubo_build(2, 2, penalty=14)           # penalty must exceed w_max
+    with pytest.raises(U.UavqError) as e:
+        U.qubo_build(30, 30)                     # w_max > 255
+    assert e.value.code == U.ETOOBIG
+    q = U.qubo_build(3, 3)
+    with pytest.raises(U.UavqError):
+        U.Plan([q], [0], 0, 10, 10.0, 1.0)       # replicas >= 1
+    with pytest.raises(U.UavqError):
+        U.Plan([q], [0], 4, 0, 10.0, 1.0)        # sweeps >= 1
+    with pytest.raises(U.UavqError):
+        U.Plan([q], [0], 4, 10, 1.0, 10.0)       # T1 <= T0
+    with pytest.raises(U.UavqError):
+        U.Plan([q], [0], 4, 10, 10.0, 1.0, dense=True)   # dense kernel needs the dense J
+    big = U.qubo_build(14, 14)                   # m = 195 > 192
+    with pytest.raises(U.UavqError) as e:
+        U.Plan([big], [0], 4, 10, 10.0, 1.0)
+    assert e.value.code == U.ETOOBIG
+
+
+def test_plan_layout(U):
+    qs = [U.qubo_build(s, s) for s in (3, 5, 9)]
+    p = U.Plan(qs, [7, 8, 9], 6, 20, 50.0, 0.5)
+    assert p.total_replicas == 18
+    assert list(p.rep_offset) == [0, 6, 12, 18]
+    sw = [q.state_words for q in qs]
+    assert list(p.state_offset) == [0, 6 * sw[0], 6 * (sw[0] + sw[1]), 6 * sum(sw)]
+    assert p.ws_bytes > 0 and p.Dmax == U.schedule(50.0, 0.5, 20, table=False)[0]
+    empty = U.Plan([], [], 4, 10, 10.0, 1.0)
+    assert empty.total_replicas == 0

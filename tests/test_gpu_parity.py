@@ -1,0 +1,156 @@
+"""GPU parity: the HIP annealer, called through the C ABI, against the CPU
+oracle on the same seeded inputs.  All annealing arithmetic is integer, so
+the bar is bit-exact equality of every trajectory output (final and best
+states, energies, best sweep, accept and draw counts)."""
+import numpy as np
+import pytest
+
+from paper_2608_25376_amd import inputs
+from tests.gpu_util import compare_replicas, gpu_anneal, say, split
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def U():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2608_25376_amd import uavq
+    uavq.lib()
+    return uavq
+
+
+def _oracle_for(oracle_lib, g, closed=True):
+    return oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed)
+
+
+def _check_instance(U, oracle_lib, g, R, S, T0, T1, seed, reps=None, closed=True, wpb=0, dense=False):
+    say(f"case: {g.rows}x{g.cols} n_free={g.n_free} inst={g.inst_id} R={R} S={S} T={T0}->{T1} seed={seed} "
+        f"closed={closed} wpb={wpb} dense={dense}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, seed, dense=dense, wpb=wpb, closed=closed)
+    gi = split(U, qs, plan, res)[0]
+    o = _oracle_for(oracle_lib, g, closed)
+    reps = list(range(R)) if reps is None else list(reps)
+    orc = oracle_lib.anneal(o, S, T0, T1, seed, g.inst_id, reps, threads=8)
+    compare_replicas(gi, orc, reps, f"{g.rows}x{g.cols}")
+    if len(reps) == R:
+        best = oracle_lib.instance_best(orc, reps)
+        assert gi["inst_best_E"] == best["best_E"]
+        assert gi["inst_best_replica"] == best["best_replica"]
+        assert gi["inst_best_sweep"] == best["best_sweep"]
+        assert (gi["inst_best_x"] == best["best_x"]).all()
+    return gi, o
+
+
+def test_grid3x3_full(U, oracle_lib):
+    """3x3, 64 replicas, 1000 sweeps, T 100 -> 0.5, seed 1: every replica."""
+    w = inputs.workload("grid3x3")
+    gi, o = _check_instance(U, oracle_lib, w.grids[0], w.replicas, w.sweeps, w.T0, w.T1, w.seed)
+    # the returned best state decodes to a tour whose cost is its energy
+    path, cost = U.decode_path(U.qubo_build(3, 3), U.pack_states(gi["inst_best_x"], o.m))
+    assert path is not None and cost == gi["inst_best_E"]
+
+
+@pytest.mark.parametrize("rows,cols,dens,inst,closed", [
+    (1, 2, 0.0, 0, True),        # m = 1
+    (2, 2, 0.0, 1, True),
+    (4, 5, 0.2, 2, True),
+    (5, 5, 0.0, 3, False),       # open path
+    (6, 7, 0.1, 4, True),
+])
+def test_small_fields_all_replicas(U, oracle_lib, rows, cols, dens, inst, closed):
+    g = inputs.grid(rows, cols, dens, seed=5, inst=inst)
+    _check_instance(U, oracle_lib, g, 37, 60, 60.0, 0.5, 11, closed=closed)
+
+
+@pytest.mark.parametrize("side,dens,inst", [(9, 0.15, 7), (11, 0.0, 8), (12, 0.0, 9)])
+def test_multi_chunk_rows(U, oracle_lib, side, dens, inst):
+    """m > 64: a step spans two or three 64-cell chunks (m = 65..143)."""
+    g = inputs.grid(side, side, dens, seed=2, inst=inst)
+    assert g.n_free > 64
+    _check_instance(U, oracle_lib, g, 9, 12, 200.0, 0.5, 3)
+
+
+def test_ragged_replicas_and_block_shapes(U, oracle_lib):
+    """Replica counts that do not fill the last block, and several
+    replicas-per-block choices, give identical bytes."""
+    g = inputs.grid(5, 6, 0.1, seed=4, inst=21)
+    base = None
+    for wpb in (1, 3, 4, 16):
+        gi, _ = _check_instance(U, oracle_lib, g, 19, 40, 80.0, 0.5, 6, wpb=wpb)
+        if base is None:
+            base = gi
+        else:
+            for f in ("final_x", "best_x", "final_E", "best_E", "accepts", "draws"):
+                assert np.array_equal(gi[f], base[f])
+
+
+def test_single_sweep_and_constant_temperature(U, oracle_lib):
+    g = inputs.grid(4, 4, 0.0, seed=1, inst=5)
+    _check_instance(U, oracle_lib, g, 8, 1, 30.0, 30.0, 2)
+    _check_instance(U, oracle_lib, g, 8, 25, 5.0, 5.0, 2)
+
+
+def test_seeded_states_and_start_sweep(U, oracle_lib):
+    """Replicas started from given states at a later sweep (the warm-start
+    interface) follow the oracle's trajectory from the same start."""
+    g = inputs.grid(6, 6, 0.1, seed=8, inst=33)
+    o = _oracle_for(oracle_lib, g)
+    R, S = 12, 50
+    rng = np.random.default_rng(1)
+    x0 = np.zeros((R, o.N), np.uint8)
+    for r in range(R):
+        X = np.zeros((o.m, o.m), np.uint8)
+        X[np.arange(o.m), rng.permutation(o.m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = (np.arange(R) % 2 == 0).astype(np.uint8)
+    start = np.where(seeded == 1, 20, 0).astype(np.int32)
+    say("case: seeded 6x6 R=12 S=50 start 20")
+    qs, plan, res = gpu_anneal(U, [g], R, S, 60.0, 0.5, 7, init_x=[x0], seeded=seeded, start_sweep=start)
+    gi = split(U, qs, plan, res)[0]
+    # oracle: seeded replicas from x0 at sweep 20, the others from random bits at 0
+    table = oracle_lib.thresholds(60.0, 0.5, S)
+    sr = [r for r in range(R) if seeded[r]]
+    ur = [r for r in range(R) if not seeded[r]]
+    o_s = oracle_lib.anneal(o, S, 60.0, 0.5, 7, g.inst_id, sr, init_x=x0[sr], start_sweep=20, table=table)
+    o_u = oracle_lib.anneal(o, S, 60.0, 0.5, 7, g.inst_id, ur, table=table)
+    compare_replicas(gi, o_s, sr, "seeded")
+    compare_replicas(gi, o_u, ur, "random")
+
+
+def test_batched_equals_single(U, oracle_lib):
+    """An instance gives the same bytes alone and inside a batch of uneven
+    instances (the random streams are addressed by instance id)."""
+    grids = inputs.batch(9, seed=3, side_lo=3, side_hi=10)
+    say("case: batch of 9, sides 3..10")
+    qs, plan, res = gpu_anneal(U, grids, 10, 30, 100.0, 0.5, 4)
+    per = split(U, qs, plan, res)
+    for i in (0, 4, 8):
+        g = grids[i]
+        q1, p1, r1 = gpu_anneal(U, [g], 10, 30, 100.0, 0.5, 4)
+        one = split(U, q1, p1, r1)[0]
+        for f in ("final_x", "best_x", "final_E", "best_E", "best_sweep", "accepts", "draws"):
+            assert np.array_equal(per[i][f], one[f]), (i, f)
+    for i, g in enumerate(grids):
+        o = _oracle_for(oracle_lib, g)
+        orc = oracle_lib.anneal(o, 30, 100.0, 0.5, 4, g.inst_id, [0, 9], threads=8)
+        compare_replicas(per[i], orc, [0, 9], f"batch inst {i}")
+
+
+def test_determinism(U):
+    g = inputs.grid(8, 8, 0.1, seed=1, inst=0)
+    say("case: determinism 8x8")
+    a = gpu_anneal(U, [g], 64, 100, 200.0, 0.5, 1)[2]
+    b = gpu_anneal(U, [g], 64, 100, 200.0, 0.5, 1)[2]
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_grid8x8_full_size_sampled(U, oracle_lib):
+    """The benchmark workload (8x8, no-fly 0.1, 1024 replicas, 2000 sweeps,
+    T 200 -> 0.5) in the benchmark's launch configuration; the oracle
+    recomputes a sample of replicas one by one."""
+    w = inputs.workload("grid8x8_nofly0.1")
+    g = w.grids[0]
+    _check_instance(U, oracle_lib, g, w.replicas, w.sweeps, w.T0, w.T1, w.seed, reps=[0, 1, 2, 511, 777, 1023])
