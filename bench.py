@@ -36,6 +36,7 @@ def parse():
     ap.add_argument("--workload", default="grid8x8_nofly0.1")
     ap.add_argument("--kernel", default="factored", choices=["factored", "dense"])
     ap.add_argument("--waves-per-block", type=int, default=0)
+    ap.add_argument("--rowmask", action="store_true", help="m <= 64: rebuild travel rows from step masks")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=0, help="oracle sample size (0 = auto)")
     return ap.parse_args()
@@ -81,7 +82,7 @@ def main():
     dense = args.kernel == "dense"
     qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly, dense=dense) for g in w.grids]
     plan = uavq.Plan(qs, [g.inst_id for g in w.grids], w.replicas, w.sweeps, w.T0, w.T1, w.seed, dense=dense,
-                     waves_per_block=args.waves_per_block)
+                     waves_per_block=args.waves_per_block, rowmask=args.rowmask)
     plan.upload()
     out = plan.alloc_outputs()
     plan.set_timing(True)

@@ -134,6 +134,8 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
 /* ------------------------------------------------------------- annealing -- */
 
 #define UAVQ_KERNEL_DENSE 0x1u   /* use the dense-field kernel (every qubo needs UAVQ_DENSE) */
+#define UAVQ_VARIANT_ROWMASK 0x10u /* m <= 64: rebuild travel rows from step masks instead of
+                                      keeping them in LDS (a schedule choice; same results) */
 
 typedef struct {
     int32_t replicas;         /* replicas per instance, >= 1 */

@@ -301,10 +301,16 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     pl->S = p->sweeps;
     pl->Dmax = Dmax;
     pl->dense = dense ? 1 : 0;
+    pl->variant = (p->flags & UAVQ_VARIANT_ROWMASK) ? UAVQ_VARIANT_ROWMASK : 0;
     const int32_t S = p->sweeps, R = p->replicas;
 
     std::vector<uint32_t> thr((size_t)S * (Dmax + 1));
     uavq_schedule(p->T0, p->T1, S, &Dmax, thr.data());
+    // device copy with rows padded to a multiple of 4 entries (16-byte rows)
+    pl->thr_stride = (Dmax + 1 + 3) & ~3;
+    std::vector<uint32_t> thr_dev((size_t)S * pl->thr_stride, 0u);
+    for (int32_t s = 0; s < S; s++)
+        std::memcpy(&thr_dev[(size_t)s * pl->thr_stride], &thr[(size_t)s * (Dmax + 1)], 4 * (size_t)(Dmax + 1));
     std::vector<int32_t> dcut(S);
     for (int32_t s = 0; s < S; s++) {
         int32_t d = 1;
@@ -331,7 +337,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
 
     // blob: thr | dcut | desc | items | inst_state_off | per-instance data
     size_t off = 0;
-    pl->thr_off = off;          off = align_up(off + thr.size() * 4, 256);
+    pl->thr_off = off;          off = align_up(off + thr_dev.size() * 4, 256);
     pl->dcut_off = off;         off = align_up(off + dcut.size() * 4, 256);
     pl->desc_off = off;         off = align_up(off + sizeof(InstDesc) * (size_t)std::max(n_inst, 1), 256);
 
@@ -386,7 +392,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         return set_error(UAVQ_ENOMEM, "plan_create: out of host memory");
     }
     uint8_t *B = pl->blob.data();
-    std::memcpy(B + pl->thr_off, thr.data(), thr.size() * 4);
+    std::memcpy(B + pl->thr_off, thr_dev.data(), thr_dev.size() * 4);
     std::memcpy(B + pl->dcut_off, dcut.data(), dcut.size() * 4);
     if (n_inst) std::memcpy(B + pl->desc_off, pl->desc.data(), sizeof(InstDesc) * n_inst);
     if (!pl->items.empty()) std::memcpy(B + pl->items_off, pl->items.data(), sizeof(WorkItem) * pl->items.size());

@@ -42,7 +42,8 @@ struct KArgs {
     const WorkItem *items;
     int32_t n_items;
     int32_t item_base;          // first item of this launch
-    const uint32_t *thr;        // S x (Dmax+1)
+    const uint32_t *thr;        // S rows of thr_stride entries (d = 0..Dmax used)
+    int32_t thr_stride;         // multiple of 4
     const int32_t *dcut;        // S: least d with thr[s][d] == 0
     int32_t S, Dmax;
     uint32_t seed;
@@ -81,7 +82,7 @@ struct uavq_qubo {
 
 struct uavq_plan {
     uavq_anneal_params p;
-    int32_t n_inst, S, Dmax;
+    int32_t n_inst, S, Dmax, thr_stride;
     std::vector<uint8_t> blob;            // static data, uploaded verbatim at offset 0
     size_t thr_off, dcut_off, desc_off, items_off, inst_state_off_off;
     size_t blob_bytes;                    // aligned size of blob
@@ -94,6 +95,7 @@ struct uavq_plan {
     int64_t total_rep, total_state_words;
     std::vector<int64_t> rep_offset, state_offset, inst_state_off;
     int32_t max_m, dense;
+    int32_t variant;                      // UAVQ_VARIANT_* (kernel choice; never changes results)
     int32_t timing = 0;                   // record events around the sweep launches
     void *ev[2 * (uavq::kMaxChunks + 1)] = {};
 };

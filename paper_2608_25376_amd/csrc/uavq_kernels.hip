@@ -47,9 +47,9 @@ static __host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~(si
 __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int i = 0; i < 10; i++) {
-        const uint32_t lo0 = 0xD2511F53u * c.x, hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t lo1 = 0xCD9E8D57u * c.z, hi1 = __umulhi(0xCD9E8D57u, c.z);
-        c = make_uint4(hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0);
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;   // one v_mad_u64_u32 each
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -61,6 +61,14 @@ __device__ __forceinline__ uint32_t pick4(uint4 v, int w) {
 }
 
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
+
+// Read-only plan data read at wave-uniform addresses: through the constant
+// address space so that it is fetched with scalar loads (no vector-memory
+// wait that would also wait for the in-flight table prefetch).
+typedef __attribute__((address_space(4))) const int32_t const_i32;
+__device__ __forceinline__ int32_t uniform_load(const int32_t *p, int i) {
+    return ((const_i32 *)p)[i];
+}
 
 // ------------------------------------------------------------------ init --
 // One block per work item; every unit (replica, 4-step block tb, word w)
@@ -157,25 +165,38 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
     return v;
 }
 
+// uint4 chunks of the next acceptance-table row held in registers while a
+// sweep runs (the rest, for small blocks, is copied directly).
+template <int NJ>
+struct Prefetch {
+    static constexpr int K = NJ == 1 ? 6 : (NJ == 2 ? 4 : 2);
+};
+
 template <int NJ>
 __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     using Ops = RowOps<NJ>;
+    constexpr int KP = Prefetch<NJ>::K;
     const WorkItem it = a.items[a.item_base + blockIdx.x];
     const InstDesc d = a.desc[it.inst];
     const int m = d.m, W = d.row_words, twoP = 2 * d.P;
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
-    const int Dw = a.Dmax + 1;
+    const int nthr = blockDim.x;
+    const int Ts = a.thr_stride;   // row stride of the acceptance table, a multiple of 4
 
-    uint8_t *sD = smem;
-    uint8_t *sdep = smem + al16((size_t)m * m);
-    uint32_t *sthr = reinterpret_cast<uint32_t *>(smem + al16((size_t)m * m) + al16((size_t)m));
+    // LDS: two acceptance-table rows | D (m*m bytes) | start-cell costs (m bytes)
+    uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
+    uint8_t *sD = smem + 8 * (size_t)Ts;
+    uint8_t *sdep = sD + al16((size_t)m * m);
     __shared__ int s_first_sh;
 
-    const uint8_t *gD = a.ws + d.d_off;
-    const uint8_t *gdep = a.ws + d.ddep_off;
-    for (int i = threadIdx.x; i < m * m; i += blockDim.x) sD[i] = gD[i];
-    for (int i = threadIdx.x; i < m; i += blockDim.x) sdep[i] = gdep[i];
+    {
+        const uint4 *gD = reinterpret_cast<const uint4 *>(a.ws + d.d_off);
+        const uint4 *gdep = reinterpret_cast<const uint4 *>(a.ws + d.ddep_off);
+        const int nD4 = (m * m + 15) >> 4, nd4 = (m + 15) >> 4;
+        for (int i = threadIdx.x; i < nD4; i += nthr) reinterpret_cast<uint4 *>(sD)[i] = gD[i];
+        for (int i = threadIdx.x; i < nd4; i += nthr) reinterpret_cast<uint4 *>(sdep)[i] = gdep[i];
+    }
 
     const bool active = wave < it.nrep;
     const int r = it.rep0 + wave;
@@ -187,9 +208,10 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
     __syncthreads();
     const int s_first = s_first_sh;
     if (s_first < a.S) {
-        const int n = a.dcut[s_first];
-        for (int i = threadIdx.x; i < n; i += blockDim.x)
-            sthr[(s_first & 1) * Dw + i] = a.thr[(size_t)s_first * Dw + i];
+        const int n4 = (a.dcut[s_first] + 3) >> 2;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
+        uint4 *dst = reinterpret_cast<uint4 *>(sthr + (s_first & 1) * Ts);
+        for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
     }
     __syncthreads();
 
@@ -229,21 +251,21 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
         uint32_t mk[2 * NJ];
 #pragma unroll
         for (int jt = 0; jt < NJ; jt++)
-        for (int lt = 0; lt < 64; lt++) {
-            const int t = 64 * jt + lt + 1;
-            if (t > m) break;
-            Ops::read(rm[jt], lt, mk);
-            const int R = Ops::popc(mk);
-            rowterm += (int64_t)d.P * R * (R - 1) - (int64_t)twoP * R;
+            for (int lt = 0; lt < 64; lt++) {
+                const int t = 64 * jt + lt + 1;
+                if (t > m) break;
+                Ops::read(rm[jt], lt, mk);
+                const int R = Ops::popc(mk);
+                rowterm += (int64_t)d.P * R * (R - 1) - (int64_t)twoP * R;
 #pragma unroll
-            for (int j = 0; j < NJ; j++) {
-                const int x = Ops::bit(mk, j, L);
-                Cc[j] += x;
-                lane_e += x * Yp[j];
-                if (t == m && d.closed && 64 * j + L < m) lane_e += x * (int)sdep[64 * j + L];
+                for (int j = 0; j < NJ; j++) {
+                    const int x = Ops::bit(mk, j, L);
+                    Cc[j] += x;
+                    lane_e += x * Yp[j];
+                    if (t == m && d.closed && 64 * j + L < m) lane_e += x * (int)sdep[64 * j + L];
+                }
+                Ops::costrow(mk, sD, m, L, Yp);
             }
-            Ops::costrow(mk, sD, m, L, Yp);
-        }
 #pragma unroll
         for (int j = 0; j < NJ; j++) lane_e += (int64_t)d.P * Cc[j] * (Cc[j] - 1);
         E = d.c0 + rowterm + wave_sum64(lane_e);
@@ -252,140 +274,170 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
     int64_t bestE = LLONG_MAX;
     int bestS = -1;
     uint64_t nacc = 0, ndraw = 0;
+    int dep[NJ];   // start-cell costs of this lane's cells (the fixed rows 0 and m+1)
+#pragma unroll
+    for (int j = 0; j < NJ; j++) {
+        const int c = 64 * j + L;
+        dep[j] = c < m ? sdep[c] : 0;
+    }
 
     for (int s = s_first; s < a.S; s++) {
-        const uint32_t *thr = sthr + (s & 1) * Dw;
-        const int dcut = a.dcut[s];
-        if (active && s >= s0) {
-            int Yp[NJ], Yc[NJ], Yn[NJ];
+        // next table row: loads issued now, stored to LDS after this sweep
+        uint4 pre[KP];
+        const bool has_next = s + 1 < a.S;
+        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 3) >> 2 : 0;
+        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
 #pragma unroll
-            for (int j = 0; j < NJ; j++) {
-                const int c = 64 * j + L;
-                Yp[j] = c < m ? sdep[c] : 0;
-            }
-            uint32_t mc[2 * NJ], mn[2 * NJ];
+        for (int k = 0; k < KP; k++) {
+            const int i = threadIdx.x + k * nthr;
+            pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        const uint32_t *thr = sthr + (s & 1) * Ts;
+        const int dcut = uniform_load(a.dcut, s);
+        if (active && s >= s0) {
+            // Yp = Y_{t-1} (final), Yc = Y_t (updated on flips), Yn = Y_{t+1}, Ynn = Y_{t+2}
+            int Yp[NJ], Yc[NJ], Yn[NJ], Ynn[NJ];
+            uint32_t mc[2 * NJ], mn[2 * NJ], mnn[2 * NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; j++) Yp[j] = dep[j];
             Ops::read(rm[0], 0, mc);
             Ops::costrow(mc, sD, m, L, Yc);
+            if (m >= 2) {
+                Ops::read(rm[0], 1, mn);
+                Ops::costrow(mn, sD, m, L, Yn);
+            } else {
+#pragma unroll
+                for (int w = 0; w < 2 * NJ; w++) mn[w] = 0u;
+#pragma unroll
+                for (int j = 0; j < NJ; j++) Yn[j] = d.closed ? dep[j] : 0;
+            }
             int blk = -1;
             uint4 u4[NJ];
 #pragma unroll
             for (int jt = 0; jt < NJ; jt++)
-            for (int lt = 0; lt < 64; lt++) {
-                const int t = 64 * jt + lt + 1;
-                if (t > m) break;
-                if (t < m) {
-                    if (lt < 63) Ops::read(rm[jt], lt + 1, mn);
-                    else Ops::read(rm[jt + 1 < NJ ? jt + 1 : jt], 0, mn);
-                    Ops::costrow(mn, sD, m, L, Yn);
-                } else {
+                for (int lt = 0; lt < 64; lt++) {
+                    const int t = 64 * jt + lt + 1;
+                    if (t > m) break;
+                    // look-ahead: Y_{t+2} from step t+2, unchanged until that step is visited
+                    if (t + 2 <= m) {
+                        const int q2 = lt + 2;
+                        if (q2 < 64) Ops::read(rm[jt], q2, mnn);
+                        else Ops::read(rm[jt + 1 < NJ ? jt + 1 : jt], q2 - 64, mnn);
+                        Ops::costrow(mnn, sD, m, L, Ynn);
+                    } else {
+#pragma unroll
+                        for (int w = 0; w < 2 * NJ; w++) mnn[w] = 0u;
+#pragma unroll
+                        for (int j = 0; j < NJ; j++) Ynn[j] = d.closed ? dep[j] : 0;
+                    }
+                    int R = Ops::popc(mc);
+                    int x[NJ], base[NJ];
 #pragma unroll
                     for (int j = 0; j < NJ; j++) {
-                        const int c = 64 * j + L;
-                        Yn[j] = (d.closed && c < m) ? sdep[c] : 0;
+                        x[j] = Ops::bit(mc, j, L);
+                        base[j] = Yp[j] + Yn[j] + twoP * (Cc[j] - 2 * x[j]) - twoP;
                     }
-                }
-                int R = Ops::popc(mc);
-                int x[NJ], base[NJ];
+                    int start = 0;
+                    bool changed = false;
+                    while (true) {
+                        const int hR = twoP * R;
+                        bool acc[NJ], need[NJ];
+                        int dE[NJ];
+                        uint64_t needm[NJ];
+                        bool any_need = false;
 #pragma unroll
-                for (int j = 0; j < NJ; j++) {
-                    x[j] = Ops::bit(mc, j, L);
-                    base[j] = Yp[j] + Yn[j] + twoP * (Cc[j] - 2 * x[j]) - twoP;
-                }
-                int start = 0;
-                bool changed = false;
-                while (true) {
-                    const int hR = twoP * R;
-                    bool acc[NJ], need[NJ];
-                    int dE[NJ];
-                    uint64_t needm[NJ];
-                    bool any_need = false;
+                        for (int j = 0; j < NJ; j++) {
+                            const int c = 64 * j + L;
+                            const int h = base[j] + hR;
+                            dE[j] = x[j] ? -h : h;
+                            const bool valid = (c >= start) && (c < m);
+                            acc[j] = valid && dE[j] <= 0;
+                            need[j] = valid && dE[j] > 0 && dE[j] < dcut;
+                            needm[j] = ballot64(need[j]);
+                            any_need |= needm[j] != 0;
+                        }
+                        if (any_need) {
+                            const int tb = (t - 1) >> 2;
+                            if (blk != tb) {
+                                uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)tb;
+                                // keeps the generator inside this branch (computed only when a draw is due)
+                                asm volatile("" : "+v"(cbase));
 #pragma unroll
-                    for (int j = 0; j < NJ; j++) {
-                        const int c = 64 * j + L;
-                        const int h = base[j] + hR;
-                        dE[j] = x[j] ? -h : h;
-                        const bool valid = (c >= start) && (c < m);
-                        acc[j] = valid && dE[j] <= 0;
-                        need[j] = valid && dE[j] > 0 && dE[j] < dcut;
-                        needm[j] = ballot64(need[j]);
-                        any_need |= needm[j] != 0;
-                    }
-                    if (any_need) {
-                        const int tb = (t - 1) >> 2;
-                        if (blk != tb) {
+                                for (int j = 0; j < NJ; j++)
+                                    u4[j] = philox(make_uint4(cbase + 64u * j, (uint32_t)s, (uint32_t)r, d.inst_id),
+                                                   a.seed, 0u);
+                                blk = tb;
+                            }
+                            const int wsel = (t - 1) & 3;
 #pragma unroll
                             for (int j = 0; j < NJ; j++)
-                                u4[j] = philox(make_uint4((uint32_t)(64 * j + L) + 65536u * (uint32_t)tb, (uint32_t)s,
-                                                          (uint32_t)r, d.inst_id),
-                                               a.seed, 0u);
-                            blk = tb;
+                                if (need[j]) acc[j] = pick4(u4[j], wsel) < thr[dE[j]];
                         }
-                        const int wsel = (t - 1) & 3;
+                        int cstar = -1;
+#pragma unroll
+                        for (int j = 0; j < NJ; j++) {
+                            const uint64_t am = ballot64(acc[j]);
+                            if (cstar < 0 && am) cstar = 64 * j + __builtin_ctzll(am);
+                        }
+                        if (cstar < 0) {
+#pragma unroll
+                            for (int j = 0; j < NJ; j++) ndraw += __popcll(needm[j]);
+                            break;
+                        }
+                        // draws taken at sites start .. cstar
+                        const int jstar = cstar >> 6, Lstar = cstar & 63;
+#pragma unroll
+                        for (int j = 0; j < NJ; j++) {
+                            if (j < jstar) ndraw += __popcll(needm[j]);
+                            else if (j == jstar)
+                                ndraw += __popcll(needm[j] & (Lstar == 63 ? ~0ull : ((2ull << Lstar) - 1ull)));
+                        }
+                        // apply the flip of (t, cstar)
+                        const int wstar = cstar >> 5;
+                        const uint32_t bstar_bit = 1u << (cstar & 31);
+                        int xs = 0;
+#pragma unroll
+                        for (int w = 0; w < 2 * NJ; w++)
+                            if (w == wstar) xs = (mc[w] & bstar_bit) ? 1 : 0;
+                        const int sign = xs ? -1 : 1;
+                        int bstar = 0;
 #pragma unroll
                         for (int j = 0; j < NJ; j++)
-                            if (need[j]) acc[j] = pick4(u4[j], wsel) < thr[dE[j]];
-                    }
-                    int cstar = -1;
+                            if (j == jstar) bstar = __builtin_amdgcn_readlane(base[j], Lstar);
+                        const int hstar = bstar + hR;
+                        E += (int64_t)(xs ? -hstar : hstar);
+                        nacc++;
 #pragma unroll
-                    for (int j = 0; j < NJ; j++) {
-                        const uint64_t am = ballot64(acc[j]);
-                        if (cstar < 0 && am) cstar = 64 * j + __builtin_ctzll(am);
-                    }
-                    if (cstar < 0) {
+                        for (int w = 0; w < 2 * NJ; w++)
+                            if (w == wstar) mc[w] ^= bstar_bit;
+                        R += sign;
+                        changed = true;
+                        const uint8_t *drow = sD + cstar * m;
 #pragma unroll
-                        for (int j = 0; j < NJ; j++) ndraw += __popcll(needm[j]);
-                        break;
-                    }
-                    // draws taken at sites start .. cstar
-                    const int jstar = cstar >> 6, Lstar = cstar & 63;
-#pragma unroll
-                    for (int j = 0; j < NJ; j++) {
-                        if (j < jstar) ndraw += __popcll(needm[j]);
-                        else if (j == jstar)
-                            ndraw += __popcll(needm[j] & (Lstar == 63 ? ~0ull : ((2ull << Lstar) - 1ull)));
-                    }
-                    // apply the flip of (t, cstar)
-                    const int wstar = cstar >> 5;
-                    const uint32_t bstar_bit = 1u << (cstar & 31);
-                    int xs = 0;
-#pragma unroll
-                    for (int w = 0; w < 2 * NJ; w++)
-                        if (w == wstar) xs = (mc[w] & bstar_bit) ? 1 : 0;
-                    const int sign = xs ? -1 : 1;
-                    int bstar = 0;
-#pragma unroll
-                    for (int j = 0; j < NJ; j++)
-                        if (j == jstar) bstar = __builtin_amdgcn_readlane(base[j], Lstar);
-                    const int hstar = bstar + hR;
-                    E += (int64_t)(xs ? -hstar : hstar);
-                    nacc++;
-#pragma unroll
-                    for (int w = 0; w < 2 * NJ; w++)
-                        if (w == wstar) mc[w] ^= bstar_bit;
-                    R += sign;
-                    changed = true;
-                    const uint8_t *drow = sD + cstar * m;
-#pragma unroll
-                    for (int j = 0; j < NJ; j++) {
-                        const int c = 64 * j + L;
-                        if (j == jstar && L == Lstar) {
-                            Cc[j] += sign;
-                            x[j] ^= 1;
+                        for (int j = 0; j < NJ; j++) {
+                            const int c = 64 * j + L;
+                            if (j == jstar && L == Lstar) {
+                                Cc[j] += sign;
+                                x[j] ^= 1;
+                            }
+                            if (c < m) Yc[j] += sign * (int)drow[c];
                         }
-                        if (c < m) Yc[j] += sign * (int)drow[c];
+                        start = cstar + 1;
+                        if (start >= m) break;
                     }
-                    start = cstar + 1;
-                    if (start >= m) break;
-                }
-                if (changed) Ops::write(rm[jt], lt, mc, L);
+                    if (changed) Ops::write(rm[jt], lt, mc, L);
 #pragma unroll
-                for (int j = 0; j < NJ; j++) {
-                    Yp[j] = Yc[j];
-                    Yc[j] = Yn[j];
-                }
+                    for (int j = 0; j < NJ; j++) {
+                        Yp[j] = Yc[j];
+                        Yc[j] = Yn[j];
+                        Yn[j] = Ynn[j];
+                    }
 #pragma unroll
-                for (int w = 0; w < 2 * NJ; w++) mc[w] = mn[w];
-            }
+                    for (int w = 0; w < 2 * NJ; w++) {
+                        mc[w] = mn[w];
+                        mn[w] = mnn[w];
+                    }
+                }
             if (E < bestE) {
                 bestE = E;
                 bestS = s;
@@ -400,11 +452,14 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
                 }
             }
         }
-        if (s + 1 < a.S) {
-            const int n = a.dcut[s + 1];
-            uint32_t *dst = sthr + ((s + 1) & 1) * Dw;
-            const uint32_t *src = a.thr + (size_t)(s + 1) * Dw;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) dst[i] = src[i];
+        if (has_next) {
+            uint4 *dst = reinterpret_cast<uint4 *>(sthr + ((s + 1) & 1) * Ts);
+#pragma unroll
+            for (int k = 0; k < KP; k++) {
+                const int i = threadIdx.x + k * nthr;
+                if (i < n4_next) dst[i] = pre[k];
+            }
+            for (int i = threadIdx.x + KP * nthr; i < n4_next; i += nthr) dst[i] = src_next[i];
         }
         __syncthreads();
     }
@@ -417,6 +472,229 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
 #pragma unroll
                 for (int w = 0; w < 2 * NJ; w++)
                     if (w < W) st[(t - 1) * W + w] = rm[j][w];
+        }
+        if (L == 0) {
+            a.final_E[grep] = E;
+            a.best_E[grep] = bestE;
+            a.best_sweep[grep] = bestS;
+            a.accepts[grep] = nacc;
+            a.draws[grep] = ndraw;
+        }
+    }
+}
+
+// ------------------------------------------------ sweep, LDS-resident rows --
+// Variant for m <= 64 (one cell per lane): lane c keeps its cell's column of
+// the state as a 64-bit step mask, and the travel rows Y_t (t = 1..m) are
+// kept in LDS (int16, one 64-entry row per step) and updated on accepts, so
+// that visiting a step costs one LDS read (issued a step ahead) and a ballot.
+// Same trajectory as k_sweep_factored bit for bit.
+__global__ __launch_bounds__(1024) void k_sweep_ylds(KArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    constexpr int KP = 6;
+    const WorkItem it = a.items[a.item_base + blockIdx.x];
+    const InstDesc d = a.desc[it.inst];
+    const int m = d.m, W = d.row_words, twoP = 2 * d.P;
+    const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
+    const int nthr = blockDim.x, nwaves = nthr >> 6;
+    const int Ts = a.thr_stride;
+
+    // LDS: two table rows | D | start-cell costs | per-wave travel rows
+    uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
+    uint8_t *sD = smem + 8 * (size_t)Ts;
+    uint8_t *sdep = sD + al16((size_t)m * m);
+    uint16_t *Yall = reinterpret_cast<uint16_t *>(sdep + al16((size_t)m));
+    uint16_t *Yw = Yall + (size_t)wave * 64 * m;   // Y_t[c] at Yw[(t-1)*64 + c]
+    __shared__ int s_first_sh;
+    (void)nwaves;
+
+    {
+        const uint4 *gD = reinterpret_cast<const uint4 *>(a.ws + d.d_off);
+        const uint4 *gdep = reinterpret_cast<const uint4 *>(a.ws + d.ddep_off);
+        const int nD4 = (m * m + 15) >> 4, nd4 = (m + 15) >> 4;
+        for (int i = threadIdx.x; i < nD4; i += nthr) reinterpret_cast<uint4 *>(sD)[i] = gD[i];
+        for (int i = threadIdx.x; i < nd4; i += nthr) reinterpret_cast<uint4 *>(sdep)[i] = gdep[i];
+    }
+    const bool active = wave < it.nrep;
+    const int r = it.rep0 + wave;
+    const int64_t grep = d.rep_base + r;
+    const int s0 = active ? (a.start_sweep ? a.start_sweep[grep] : 0) : a.S;
+    if (threadIdx.x == 0) s_first_sh = a.S;
+    __syncthreads();
+    if (L == 0) atomicMin(&s_first_sh, s0);
+    __syncthreads();
+    const int s_first = s_first_sh;
+    if (s_first < a.S) {
+        const int n4 = (uniform_load(a.dcut, s_first) + 3) >> 2;
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
+        uint4 *dst = reinterpret_cast<uint4 *>(sthr + (s_first & 1) * Ts);
+        for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
+    }
+    __syncthreads();
+
+    const bool lane_in = L < m;
+    const uint64_t lanes_m = m >= 64 ? ~0ull : ((1ull << m) - 1ull);
+    const int dep = lane_in ? (int)sdep[L] : 0;
+    uint32_t *st = a.states + d.state_off + (int64_t)r * d.state_words;
+
+    // ---- initial state: rows (lane L holds step L+1) -> columns, counts, travel rows, energy
+    uint64_t cm = 0;      // bit t-1: x_{t, L}
+    int Cc = 0;
+    int64_t E = 0;
+    if (active) {
+        uint32_t rw0 = 0u, rw1 = 0u;
+        if (lane_in) {
+            rw0 = st[L * W];
+            if (W > 1) rw1 = st[L * W + 1];
+            uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
+            bs[L * W] = rw0;
+            if (W > 1) bs[L * W + 1] = rw1;
+        }
+        int64_t lane_e = 0, rowterm = 0;
+        int Yp = dep;
+        for (int t = 1; t <= m; t++) {
+            const uint32_t r0 = __builtin_amdgcn_readlane(rw0, t - 1);
+            const uint32_t r1 = __builtin_amdgcn_readlane(rw1, t - 1);
+            const uint64_t row = ((uint64_t)r1 << 32) | r0;
+            const int x = lane_in ? (int)((row >> L) & 1ull) : 0;
+            cm |= (uint64_t)x << (t - 1);
+            Cc += x;
+            const int R = __popcll(row);
+            rowterm += (int64_t)d.P * R * (R - 1) - (int64_t)twoP * R;
+            lane_e += x * Yp;
+            if (t == m && d.closed) lane_e += x * dep;
+            int Yt = 0;
+            uint64_t bits = row;
+            while (bits) {
+                const int b = __builtin_ctzll(bits);
+                bits &= bits - 1ull;
+                if (lane_in) Yt += sD[b * m + L];
+            }
+            Yw[(t - 1) * 64 + L] = (uint16_t)Yt;
+            Yp = Yt;
+        }
+        lane_e += (int64_t)d.P * Cc * (Cc - 1);
+        E = d.c0 + rowterm + wave_sum64(lane_e);
+    }
+
+    int64_t bestE = LLONG_MAX;
+    int bestS = -1;
+    uint64_t bestcm = cm;
+    uint64_t nacc = 0, ndraw = 0;
+    const int closed_dep = d.closed ? dep : 0;
+
+    for (int s = s_first; s < a.S; s++) {
+        uint4 pre[KP];
+        const bool has_next = s + 1 < a.S;
+        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 3) >> 2 : 0;
+        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
+#pragma unroll
+        for (int k = 0; k < KP; k++) {
+            const int i = threadIdx.x + k * nthr;
+            pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
+        }
+        const uint32_t *thr = sthr + (s & 1) * Ts;
+        const int dcut = uniform_load(a.dcut, s);
+        if (active && s >= s0) {
+            int Yp = dep;
+            int Yc = Yw[L];
+            int Yn = m >= 2 ? (int)Yw[64 + L] : closed_dep;
+            int blk = -1;
+            uint4 u4 = make_uint4(0u, 0u, 0u, 0u);
+            for (int t = 1; t <= m; t++) {
+                // travel row of step t+2 (read a step ahead)
+                const int Ynn = (t + 2 <= m) ? (int)Yw[(t + 1) * 64 + L] : closed_dep;
+                const int xb = (int)((cm >> (t - 1)) & 1ull);
+                uint64_t rmask = ballot64(xb != 0);
+                int R = __popcll(rmask);
+                const int negx = -xb;
+                const int base = Yp + Yn + twoP * (Cc - 2 * xb - 1);
+                uint64_t open = lanes_m;
+                bool changed = false;
+                while (true) {
+                    const int h = base + twoP * R;
+                    const int dE = (h ^ negx) - negx;
+                    const bool mine = (open >> L) & 1ull;
+                    uint64_t accm = ballot64(mine && dE <= 0);
+                    const bool need = mine && dE > 0 && dE < dcut;
+                    const uint64_t needm = ballot64(need);
+                    if (needm) {
+                        const int tb = (t - 1) >> 2;
+                        if (blk != tb) {
+                            uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)tb;
+                            asm volatile("" : "+v"(cbase));   // generator stays inside this branch
+                            u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
+                            blk = tb;
+                        }
+                        uint32_t thv = 0u;
+                        if (need) thv = thr[dE];
+                        accm |= ballot64(need && pick4(u4, (t - 1) & 3) < thv);
+                    }
+                    if (!accm) {
+                        ndraw += __popcll(needm);
+                        break;
+                    }
+                    const int cstar = __builtin_ctzll(accm);
+                    const uint64_t upto = cstar == 63 ? ~0ull : ((2ull << cstar) - 1ull);
+                    ndraw += __popcll(needm & upto);
+                    E += (int64_t)__builtin_amdgcn_readlane(dE, cstar);
+                    nacc++;
+                    const int sign = ((rmask >> cstar) & 1ull) ? -1 : 1;
+                    rmask ^= 1ull << cstar;
+                    R += sign;
+                    if (L == cstar) {
+                        cm ^= 1ull << (t - 1);
+                        Cc += sign;
+                    }
+                    if (lane_in) Yc += sign * (int)sD[cstar * m + L];
+                    changed = true;
+                    open &= ~upto;
+                    if (!open) break;
+                }
+                if (changed) Yw[(t - 1) * 64 + L] = (uint16_t)Yc;
+                Yp = Yc;
+                Yc = Yn;
+                Yn = Ynn;
+            }
+            if (E < bestE) {
+                bestE = E;
+                bestS = s;
+                bestcm = cm;
+            }
+        }
+        if (has_next) {
+            uint4 *dst = reinterpret_cast<uint4 *>(sthr + ((s + 1) & 1) * Ts);
+#pragma unroll
+            for (int k = 0; k < KP; k++) {
+                const int i = threadIdx.x + k * nthr;
+                if (i < n4_next) dst[i] = pre[k];
+            }
+            for (int i = threadIdx.x + KP * nthr; i < n4_next; i += nthr) dst[i] = src_next[i];
+        }
+        __syncthreads();
+    }
+
+    if (active) {
+        // columns -> rows for the final and best states
+        uint32_t f0 = 0u, f1 = 0u, b0 = 0u, b1 = 0u;
+        for (int t = 1; t <= m; t++) {
+            const uint64_t fr = ballot64((cm >> (t - 1)) & 1ull);
+            const uint64_t br = ballot64((bestcm >> (t - 1)) & 1ull);
+            if (L == t - 1) {
+                f0 = (uint32_t)fr;
+                f1 = (uint32_t)(fr >> 32);
+                b0 = (uint32_t)br;
+                b1 = (uint32_t)(br >> 32);
+            }
+        }
+        if (lane_in) {
+            st[L * W] = f0;
+            if (W > 1) st[L * W + 1] = f1;
+            if (bestS >= 0) {
+                uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
+                bs[L * W] = b0;
+                if (W > 1) bs[L * W + 1] = b1;
+            }
         }
         if (L == 0) {
             a.final_E[grep] = E;
@@ -479,7 +757,7 @@ static int launch_factored_class(const uavq_plan *pl, KArgs a, int cls, hipStrea
     if (b1 <= b0) return UAVQ_OK;
     int mmax = 0;
     for (int i = b0; i < b1; i++) mmax = std::max(mmax, pl->desc[pl->items[i].inst].m);
-    const size_t lds = al16((size_t)mmax * mmax) + al16((size_t)mmax) + 2 * (size_t)(pl->Dmax + 1) * 4;
+    const size_t lds = 8 * (size_t)pl->thr_stride + al16((size_t)mmax * mmax) + al16((size_t)mmax);
     if (lds > 160 * 1024)
         return set_error(UAVQ_ETOOBIG, "anneal: LDS need %zu bytes (m = %d, Dmax = %d)", lds, mmax, pl->Dmax);
     UAVQ_HIP(hipFuncSetAttribute((const void *)k_sweep_factored<NJ>, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -493,6 +771,33 @@ static int launch_factored_class(const uavq_plan *pl, KArgs a, int cls, hipStrea
     return UAVQ_OK;
 }
 
+static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
+    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + (size_t)wpb * 64 * m * 2;
+}
+
+// chunk class 1 (m <= 64) with the LDS-resident travel rows
+static int launch_ylds_class(const uavq_plan *pl, KArgs a, hipStream_t st) {
+    const int b0 = pl->class_begin[1], b1 = pl->class_begin[2];
+    if (b1 <= b0) return UAVQ_OK;
+    int mmax = 0;
+    for (int i = b0; i < b1; i++) mmax = std::max(mmax, pl->desc[pl->items[i].inst].m);
+    const int wpb = pl->waves_per_block[1];
+    const size_t lds = ylds_lds_bytes(pl, mmax, wpb);
+    UAVQ_HIP(hipFuncSetAttribute((const void *)k_sweep_ylds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    a.item_base = b0;
+    if (pl->timing) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2], st));
+    hipLaunchKernelGGL(k_sweep_ylds, dim3(b1 - b0), dim3(64 * wpb), lds, st, a);
+    if (pl->timing) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[3], st));
+    UAVQ_HIP(hipGetLastError());
+    return UAVQ_OK;
+}
+
+bool ylds_fits(const uavq_plan *pl) {
+    int mmax = 0;
+    for (int i = pl->class_begin[1]; i < pl->class_begin[2]; i++) mmax = std::max(mmax, pl->desc[pl->items[i].inst].m);
+    return ylds_lds_bytes(pl, mmax, pl->waves_per_block[1]) <= 160 * 1024;
+}
+
 int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *check_E) {
     hipStream_t st = (hipStream_t)stream;
     KArgs a = a0;
@@ -504,7 +809,11 @@ int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *c
     hipLaunchKernelGGL(k_init_states, dim3(n_items), dim3(256), 0, st, a);
     UAVQ_HIP(hipGetLastError());
     int rc;
-    if ((rc = launch_factored_class<1>(pl, a, 1, st))) return rc;
+    if (pl->variant != UAVQ_VARIANT_ROWMASK && ylds_fits(pl)) {
+        if ((rc = launch_ylds_class(pl, a, st))) return rc;
+    } else if ((rc = launch_factored_class<1>(pl, a, 1, st))) {
+        return rc;
+    }
     if ((rc = launch_factored_class<2>(pl, a, 2, st))) return rc;
     if ((rc = launch_factored_class<3>(pl, a, 3, st))) return rc;
     hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
@@ -551,6 +860,7 @@ int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const ua
     a.dcut = (const int32_t *)(ws + pl->dcut_off);
     a.S = pl->S;
     a.Dmax = pl->Dmax;
+    a.thr_stride = pl->thr_stride;
     a.seed = pl->p.seed;
     a.n_inst = pl->n_inst;
     a.total_rep = pl->total_rep;

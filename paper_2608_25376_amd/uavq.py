@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(HERE, "libuavq.so")
 OPEN_PATH = 0x1
 DENSE = 0x2
 KERNEL_DENSE = 0x1
+VARIANT_ROWMASK = 0x10
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
 
@@ -264,13 +265,15 @@ class Plan:
     """uavq_plan_create + workspace; call ``upload`` once, then ``anneal``."""
 
     def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
-                 T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0):
+                 T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
+                 rowmask: bool = False):
         self.qubos = list(qubos)
         n = len(self.qubos)
         arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in self.qubos])
         ids = np.ascontiguousarray(inst_ids, dtype=np.uint32)
         assert ids.size == n
-        p = _Params(replicas, sweeps, T0, T1, seed, KERNEL_DENSE if dense else 0, waves_per_block)
+        flags = (KERNEL_DENSE if dense else 0) | (VARIANT_ROWMASK if rowmask else 0)
+        p = _Params(replicas, sweeps, T0, T1, seed, flags, waves_per_block)
         h = C.c_void_p()
         _check(lib().uavq_plan_create(arr, n, _np_ptr(ids, C.c_uint32), C.byref(p), C.byref(h)))
         self._h = h

@@ -25,10 +25,11 @@ def _oracle_for(oracle_lib, g, closed=True):
     return oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed)
 
 
-def _check_instance(U, oracle_lib, g, R, S, T0, T1, seed, reps=None, closed=True, wpb=0, dense=False):
+def _check_instance(U, oracle_lib, g, R, S, T0, T1, seed, reps=None, closed=True, wpb=0, dense=False,
+                    rowmask=False):
     say(f"case: {g.rows}x{g.cols} n_free={g.n_free} inst={g.inst_id} R={R} S={S} T={T0}->{T1} seed={seed} "
-        f"closed={closed} wpb={wpb} dense={dense}")
-    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, seed, dense=dense, wpb=wpb, closed=closed)
+        f"closed={closed} wpb={wpb} dense={dense} rowmask={rowmask}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, seed, dense=dense, wpb=wpb, closed=closed, rowmask=rowmask)
     gi = split(U, qs, plan, res)[0]
     o = _oracle_for(oracle_lib, g, closed)
     reps = list(range(R)) if reps is None else list(reps)
@@ -72,13 +73,22 @@ def test_multi_chunk_rows(U, oracle_lib, side, dens, inst):
     _check_instance(U, oracle_lib, g, 9, 12, 200.0, 0.5, 3)
 
 
+@pytest.mark.parametrize("rows,cols,dens,inst,closed", [
+    (1, 2, 0.0, 0, True), (3, 3, 0.0, 1, True), (5, 5, 0.0, 3, False), (8, 8, 0.1, 0, True)])
+def test_rowmask_variant(U, oracle_lib, rows, cols, dens, inst, closed):
+    """The m <= 64 kernel that rebuilds travel rows from step masks (instead
+    of keeping them in LDS) follows the same trajectories."""
+    g = inputs.grid(rows, cols, dens, seed=5, inst=inst)
+    _check_instance(U, oracle_lib, g, 21, 50, 100.0, 0.5, 13, closed=closed, rowmask=True)
+
+
 def test_ragged_replicas_and_block_shapes(U, oracle_lib):
-    """Replica counts that do not fill the last block, and several
-    replicas-per-block choices, give identical bytes."""
+    """Replica counts that do not fill the last block, several
+    replicas-per-block choices and both m <= 64 kernels give identical bytes."""
     g = inputs.grid(5, 6, 0.1, seed=4, inst=21)
     base = None
-    for wpb in (1, 3, 4, 16):
-        gi, _ = _check_instance(U, oracle_lib, g, 19, 40, 80.0, 0.5, 6, wpb=wpb)
+    for wpb, rm in ((1, False), (3, False), (4, False), (16, False), (4, True), (7, True)):
+        gi, _ = _check_instance(U, oracle_lib, g, 19, 40, 80.0, 0.5, 6, wpb=wpb, rowmask=rm)
         if base is None:
             base = gi
         else:
