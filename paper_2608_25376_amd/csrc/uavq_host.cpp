@@ -287,6 +287,8 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     for (int32_t i = 0; i < n_inst; i++) {
         if (!q[i]) return set_error(UAVQ_EINVAL, "plan_create: null qubo %d", i);
         if (dense && q[i]->J.empty()) return set_error(UAVQ_EINVAL, "plan_create: dense kernel needs UAVQ_DENSE (instance %d)", i);
+        if (dense && q[i]->N > 4096)
+            return set_error(UAVQ_ETOOBIG, "plan_create: dense kernel holds at most 4096 variables (N = %d)", q[i]->N);
         if (!dense && q[i]->m > kMaxM)
             return set_error(UAVQ_ETOOBIG, "plan_create: m = %d exceeds the factored kernel's %d", q[i]->m, kMaxM);
     }
@@ -373,10 +375,13 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         d.d_off = (int64_t)off;     off = align_up(off + qi->D.size(), 16);
         d.ddep_off = (int64_t)off;  off = align_up(off + qi->ddep.size(), 256);
         if (dense) {
-            d.J_off = (int64_t)off; off = align_up(off + qi->J.size() * 2, 256);
-            d.b_off = (int64_t)off; off = align_up(off + qi->b.size() * 4, 256);
+            const size_t Np = ((size_t)qi->N + 31) / 32 * 32;
+            d.J_off = (int64_t)off;     off = align_up(off + qi->J.size() * 2, 256);
+            d.Jlimb_off = (int64_t)off; off = align_up(off + 2 * Np * Np, 256);
+            d.b_off = (int64_t)off;     off = align_up(off + qi->b.size() * 4, 256);
         } else {
             d.J_off = -1;
+            d.Jlimb_off = -1;
             d.b_off = -1;
         }
         d.rep_base = pl->rep_offset[i];
@@ -405,10 +410,31 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         if (dense) {
             std::memcpy(B + d.J_off, qi->J.data(), qi->J.size() * 2);
             std::memcpy(B + d.b_off, qi->b.data(), qi->b.size() * 4);
+            // int8 limbs J = lo + 128 hi for the MFMA field refresh (rows padded to Np)
+            const size_t N = (size_t)qi->N, Np = (N + 31) / 32 * 32;
+            int8_t *lo = reinterpret_cast<int8_t *>(B + d.Jlimb_off), *hi = lo + Np * Np;
+            for (size_t k = 0; k < N; k++)
+                for (size_t l = 0; l < N; l++) {
+                    const int v = qi->J[k * N + l];
+                    lo[k * Np + l] = (int8_t)(v & 127);
+                    hi[k * Np + l] = (int8_t)(v >> 7);
+                }
         }
     }
     pl->e_init_off = pl->blob_bytes;
-    pl->ws_bytes = align_up(pl->e_init_off + 8 * (size_t)std::max<int64_t>(pl->total_rep, 1), 256);
+    size_t wsoff = align_up(pl->e_init_off + 8 * (size_t)std::max<int64_t>(pl->total_rep, 1), 256);
+    pl->dense_xb_off = pl->dense_h_off = 0;
+    if (dense) {
+        size_t xb = 0, hb = 0;
+        for (int32_t i = 0; i < n_inst; i++) {
+            const size_t N = (size_t)q[i]->N, Np = (N + 31) / 32 * 32;
+            xb = std::max(xb, (size_t)R * Np);
+            hb = std::max(hb, (size_t)R * N * 4);
+        }
+        pl->dense_xb_off = wsoff; wsoff = align_up(wsoff + xb, 256);
+        pl->dense_h_off = wsoff;  wsoff = align_up(wsoff + hb, 256);
+    }
+    pl->ws_bytes = wsoff;
     *out = pl;
     return UAVQ_OK;
 }

@@ -6,6 +6,8 @@
 
 #include "../../include/uavq.h"
 
+typedef struct ihipStream_t *hipStream_t_opaque;
+
 namespace uavq {
 
 // Largest number of 64-column chunks a replica row may span in the factored
@@ -23,6 +25,7 @@ struct InstDesc {
     int64_t d_off;      // byte offset of D (m*m uint8, row-major)
     int64_t ddep_off;   // byte offset of the start-cell costs (m uint8)
     int64_t J_off;      // byte offset of the dense J (N*N int16) or -1
+    int64_t Jlimb_off;  // byte offset of the J limbs (two Np*Np int8: J & 127, J >> 7) or -1
     int64_t b_off;      // byte offset of b (N int32) or -1
     int64_t rep_base;   // global index of replica 0
     int64_t state_off;  // word offset of replica 0's state
@@ -87,6 +90,7 @@ struct uavq_plan {
     size_t thr_off, dcut_off, desc_off, items_off, inst_state_off_off;
     size_t blob_bytes;                    // aligned size of blob
     size_t e_init_off;                    // int64 per replica
+    size_t dense_xb_off, dense_h_off;     // dense kernel: unpacked states, refreshed fields
     size_t ws_bytes;
     std::vector<uavq::InstDesc> desc;
     std::vector<uavq::WorkItem> items;    // ordered by chunk class, then LPT
@@ -105,6 +109,9 @@ extern "C" void plan_destroy_events(uavq_plan *pl);
 // Kernel launchers (uavq_kernels.hip).
 namespace uavq {
 int launch_anneal(const uavq_plan *plan, const KArgs &a, void *stream, int64_t *check_E);
+int launch_dense(const uavq_plan *plan, const KArgs &a, hipStream_t_opaque st);
+int launch_energy_refresh(const uint32_t *d_states, int64_t n, int64_t *d_E, const uint8_t *d_D, const uint8_t *d_dep,
+                          int m, int P, int closed, int64_t c0, hipStream_t_opaque st);
 int launch_energy(const uavq_qubo *q, const uint32_t *d_x, int64_t n, int64_t *d_E, void *d_ws,
                   size_t ws_bytes, void *stream);
 size_t energy_ws_bytes(const uavq_qubo *q);

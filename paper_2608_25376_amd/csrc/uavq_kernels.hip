@@ -30,45 +30,9 @@
 #include <climits>
 #include <cstdint>
 
-#include "uavq_internal.h"
+#include "uavq_device.h"
 
 namespace uavq {
-
-#define UAVQ_HIP(call)                                                                   \
-    do {                                                                                 \
-        hipError_t e_ = (call);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return set_error(UAVQ_EHIP, "%s: %s", #call, hipGetErrorString(e_));         \
-    } while (0)
-
-static __host__ __device__ inline size_t al16(size_t v) { return (v + 15) & ~(size_t)15; }
-
-// Philox4x32-10 (Salmon et al., SC'11).
-__device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int i = 0; i < 10; i++) {
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;   // one v_mad_u64_u32 each
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        c = make_uint4((uint32_t)(p1 >> 32) ^ c.y ^ k0, (uint32_t)p1, (uint32_t)(p0 >> 32) ^ c.w ^ k1, (uint32_t)p0);
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-    return c;
-}
-
-__device__ __forceinline__ uint32_t pick4(uint4 v, int w) {
-    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
-}
-
-__device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
-
-// Read-only plan data read at wave-uniform addresses: through the constant
-// address space so that it is fetched with scalar loads (no vector-memory
-// wait that would also wait for the in-flight table prefetch).
-typedef __attribute__((address_space(4))) const int32_t const_i32;
-__device__ __forceinline__ int32_t uniform_load(const int32_t *p, int i) {
-    return ((const_i32 *)p)[i];
-}
 
 // ------------------------------------------------------------------ init --
 // One block per work item; every unit (replica, 4-step block tb, word w)
@@ -159,11 +123,6 @@ struct RowOps {
     }
 };
 
-__device__ __forceinline__ int64_t wave_sum64(int64_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
 
 // uint4 chunks of the next acceptance-table row held in registers while a
 // sweep runs (the rest, for small blocks, is copied directly).
@@ -798,17 +757,32 @@ bool ylds_fits(const uavq_plan *pl) {
     return ylds_lds_bytes(pl, mmax, pl->waves_per_block[1]) <= 160 * 1024;
 }
 
+// energies of the final states recomputed by the MFMA refresh (invariant check)
+static int launch_checks(const uavq_plan *pl, const KArgs &a, int64_t *check_E, hipStream_t st) {
+    for (int i = 0; i < pl->n_inst; i++) {
+        const InstDesc &d = pl->desc[i];
+        int rc = launch_energy_refresh(a.states + d.state_off, d.nrep, check_E + d.rep_base, a.ws + d.d_off,
+                                       a.ws + d.ddep_off, d.m, d.P, d.closed, d.c0, st);
+        if (rc) return rc;
+    }
+    return UAVQ_OK;
+}
+
 int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *check_E) {
     hipStream_t st = (hipStream_t)stream;
     KArgs a = a0;
     const int n_items = (int)pl->items.size();
     if (n_items == 0) return UAVQ_OK;
-    if (check_E) return set_error(UAVQ_EINVAL, "anneal: check_E not supported yet");
-    if (pl->dense) return set_error(UAVQ_EINVAL, "anneal: dense kernel not built yet");
     a.item_base = 0;
     hipLaunchKernelGGL(k_init_states, dim3(n_items), dim3(256), 0, st, a);
     UAVQ_HIP(hipGetLastError());
     int rc;
+    if (pl->dense) {
+        if ((rc = launch_dense(pl, a, st))) return rc;
+        hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
+        UAVQ_HIP(hipGetLastError());
+        return check_E ? launch_checks(pl, a, check_E, st) : UAVQ_OK;
+    }
     if (pl->variant != UAVQ_VARIANT_ROWMASK && ylds_fits(pl)) {
         if ((rc = launch_ylds_class(pl, a, st))) return rc;
     } else if ((rc = launch_factored_class<1>(pl, a, 1, st))) {
@@ -818,13 +792,22 @@ int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *c
     if ((rc = launch_factored_class<3>(pl, a, 3, st))) return rc;
     hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
     UAVQ_HIP(hipGetLastError());
-    return UAVQ_OK;
+    return check_E ? launch_checks(pl, a, check_E, st) : UAVQ_OK;
 }
 
-size_t energy_ws_bytes(const uavq_qubo *q) { return q ? 256 : 0; }
+size_t energy_ws_bytes(const uavq_qubo *q) {
+    return q ? ((size_t)q->m * q->m + 255) / 256 * 256 + ((size_t)q->m + 255) / 256 * 256 : 0;
+}
 
-int launch_energy(const uavq_qubo *, const uint32_t *, int64_t, int64_t *, void *, size_t, void *) {
-    return set_error(UAVQ_EINVAL, "energy_eval_dev: not built yet");
+int launch_energy(const uavq_qubo *q, const uint32_t *d_x, int64_t n, int64_t *d_E, void *d_ws, size_t ws_bytes,
+                  void *stream) {
+    if (!d_ws || ws_bytes < energy_ws_bytes(q)) return set_error(UAVQ_EINVAL, "energy_eval_dev: workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t *dD = (uint8_t *)d_ws;
+    uint8_t *ddep = dD + ((size_t)q->m * q->m + 255) / 256 * 256;
+    UAVQ_HIP(hipMemcpyAsync(dD, q->D.data(), q->D.size(), hipMemcpyHostToDevice, st));
+    UAVQ_HIP(hipMemcpyAsync(ddep, q->ddep.data(), q->ddep.size(), hipMemcpyHostToDevice, st));
+    return launch_energy_refresh(d_x, n, d_E, dD, ddep, q->m, q->P, q->closed, q->c0, st);
 }
 
 }  // namespace uavq
