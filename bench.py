@@ -37,6 +37,9 @@ def parse():
     ap.add_argument("--kernel", default="factored", choices=["factored", "dense"])
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--rowmask", action="store_true", help="m <= 64: rebuild travel rows from step masks")
+    ap.add_argument("--persistent", action="store_true", help="persistent work-queue sweep kernels")
+    ap.add_argument("--graph", action="store_true", help="replay anneal_batch as a captured HIP graph")
+    ap.add_argument("--autotune", action="store_true", help="choose the launch shape with uavq_autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=0, help="oracle sample size (0 = auto)")
     return ap.parse_args()
@@ -81,15 +84,24 @@ def main():
     w = inputs.workload(args.workload)
     dense = args.kernel == "dense"
     qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly, dense=dense) for g in w.grids]
-    plan = uavq.Plan(qs, [g.inst_id for g in w.grids], w.replicas, w.sweeps, w.T0, w.T1, w.seed, dense=dense,
-                     waves_per_block=args.waves_per_block, rowmask=args.rowmask)
-    plan.upload()
+    ids = [g.inst_id for g in w.grids]
+    tune = None
+    if args.autotune:
+        tune = uavq.autotune(qs, ids, w.replicas, w.sweeps, w.T0, w.T1, w.seed, persistent=args.persistent,
+                             trial_sweeps=max(16, w.sweeps // 32),
+                             cache=os.path.join(ROOT, "paper_2608_25376_amd", "tune_cache.json"))
+    stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
+    plan = uavq.Plan(qs, ids, w.replicas, w.sweeps, w.T0, w.T1, w.seed, dense=dense,
+                     waves_per_block=args.waves_per_block, rowmask=args.rowmask, persistent=args.persistent,
+                     graph=args.graph, tune=tune)
+    plan.upload(stream=stream if args.graph else None)
     out = plan.alloc_outputs()
-    plan.set_timing(True)
-    stream = torch.cuda.current_stream()
+    torch.cuda.synchronize()
+    if not args.graph:
+        plan.set_timing(True)
 
     for _ in range(args.warmup):
-        plan.anneal(out=out)
+        plan.anneal(out=out, stream=stream)
     torch.cuda.synchronize()
 
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -97,10 +109,12 @@ def main():
     torch.cuda.synchronize()
     start.record(stream)
     for _ in range(args.steps):
-        plan.anneal(out=out)
-        # the library's events bracket the sweep kernel of this call
-        torch.cuda.current_stream().synchronize()
-        sweep_ms.append(plan.sweep_ms())
+        plan.anneal(out=out, stream=stream)
+        # the library's events bracket the sweep kernels of this call (in graph
+        # mode the whole replayed graph is timed instead)
+        stream.synchronize()
+        if not args.graph:
+            sweep_ms.append(plan.sweep_ms())
     stop.record(stream)
     torch.cuda.synchronize()
     total_ms = start.elapsed_time(stop)
@@ -112,7 +126,7 @@ def main():
     drw = out.draws.cpu().numpy().astype(np.float64)
     m_per_rep = np.concatenate([np.full(w.replicas, q.m) for q in qs]).astype(np.float64)
     ops = OPS_PER_ATTEMPT * attempts + OPS_PER_DRAW * drw.sum() + ((m_per_rep + OPS_PER_ACCEPT_BASE) * acc).sum()
-    sweep_avg = float(np.mean(sweep_ms))
+    sweep_avg = float(np.mean(sweep_ms)) if sweep_ms else ms_per_step
     achieved = ops / (sweep_avg * 1e-3)
     value = attempts / (ms_per_step * 1e-3)
 
@@ -131,7 +145,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "instances": len(qs), "m": int(qs[0].m) if len(qs) == 1 else None,
                    "n_vars": n_vars, "replicas": w.replicas, "sweeps": w.sweeps, "T0": w.T0, "T1": w.T1,
-                   "seed": w.seed, "kernel": args.kernel, "attempts_per_step": attempts,
+                   "seed": w.seed, "kernel": args.kernel, "persistent": args.persistent, "graph": args.graph,
+                   "tune": repr(tune) if tune is not None else None, "attempts_per_step": attempts,
                    "accept_rate": float(acc.sum() / attempts), "draw_rate": float(drw.sum() / attempts),
                    "best_E": [int(v) for v in out.inst_best_E.cpu().numpy()[:4]]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12,

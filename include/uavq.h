@@ -136,6 +136,18 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
 #define UAVQ_KERNEL_DENSE 0x1u   /* use the dense-field kernel (every qubo needs UAVQ_DENSE) */
 #define UAVQ_VARIANT_ROWMASK 0x10u /* m <= 64: rebuild travel rows from step masks instead of
                                       keeping them in LDS (a schedule choice; same results) */
+#define UAVQ_PERSISTENT 0x20u      /* persistent sweep kernels: an occupancy-sized grid pulls
+                                      work items (largest instances first) from a counter */
+#define UAVQ_GRAPH 0x40u           /* capture the launch sequence of anneal_batch into a HIP graph
+                                      on first use and replay it while the buffers and stream are
+                                      the same; needs a non-default stream */
+
+/* Launch shape chosen by uavq_autotune (never changes results). */
+typedef struct {
+    int32_t waves_per_block[4];  /* per chunk class c = ceil(m/64) (index 0 unused); 0 = default */
+    uint32_t variant_flags;      /* 0 or UAVQ_VARIANT_ROWMASK */
+    float trial_ms;              /* measured time of the chosen shape (trial run) */
+} uavq_tune;
 
 typedef struct {
     int32_t replicas;         /* replicas per instance, >= 1 */
@@ -145,6 +157,7 @@ typedef struct {
     uint32_t flags;           /* UAVQ_KERNEL_DENSE */
     int32_t waves_per_block;  /* replicas per workgroup; 0 = library choice.
                                  Never changes results. */
+    const uavq_tune *tune;    /* optional per-class launch shape (overrides the two above) */
 } uavq_anneal_params;
 
 typedef struct uavq_plan uavq_plan;
@@ -206,6 +219,15 @@ typedef struct {              /* device outputs, caller-owned; NULL = not wanted
  * Asynchronous on `stream`; outputs are valid once the stream has drained. */
 int uavq_anneal_batch(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
                       const uavq_anneal_out *out, void *stream);
+
+/* Autotuner: times anneal_batch launch shapes (replicas per workgroup per
+ * chunk class, m <= 64 kernel variant) on a short trial of trial_sweeps
+ * sweeps of these instances, with device memory it allocates and frees
+ * itself, and returns the fastest in *out.  With cache_path != NULL the choice
+ * is read from / written to that JSON file, keyed by device, replicas and the
+ * instance-size classes.  Every shape gives identical results. */
+int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *inst_ids,
+                  const uavq_anneal_params *p, int32_t trial_sweeps, const char *cache_path, uavq_tune *out);
 
 /* Kernel timing for measurement: when enabled, uavq_anneal_batch records HIP
  * events on its stream around the sweep-kernel launches of this plan, and

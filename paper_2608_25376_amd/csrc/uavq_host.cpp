@@ -304,6 +304,9 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     pl->Dmax = Dmax;
     pl->dense = dense ? 1 : 0;
     pl->variant = (p->flags & UAVQ_VARIANT_ROWMASK) ? UAVQ_VARIANT_ROWMASK : 0;
+    if (p->tune) pl->variant = p->tune->variant_flags & UAVQ_VARIANT_ROWMASK;
+    pl->persistent = (p->flags & UAVQ_PERSISTENT) ? 1 : 0;
+    pl->graph = (p->flags & UAVQ_GRAPH) ? 1 : 0;
     const int32_t S = p->sweeps, R = p->replicas;
 
     std::vector<uint32_t> thr((size_t)S * (Dmax + 1));
@@ -352,6 +355,11 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     for (int c = 0; c <= kMaxChunks + 1; c++) pl->class_begin[c] = 0;
     for (int cls = 1; cls <= kMaxChunks; cls++) {
         int wpb = p->waves_per_block ? p->waves_per_block : default_waves_per_block(cls);
+        if (p->tune && p->tune->waves_per_block[cls] > 0) wpb = p->tune->waves_per_block[cls];
+        if (wpb < 1 || wpb > 16) {
+            delete pl;
+            return set_error(UAVQ_EINVAL, "plan_create: waves per block %d out of range", wpb);
+        }
         pl->waves_per_block[cls] = wpb;
         pl->class_begin[cls] = (int32_t)pl->items.size();
         for (int32_t i : order) {
@@ -434,6 +442,8 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         pl->dense_xb_off = wsoff; wsoff = align_up(wsoff + xb, 256);
         pl->dense_h_off = wsoff;  wsoff = align_up(wsoff + hb, 256);
     }
+    pl->queue_off = wsoff;
+    wsoff = align_up(wsoff + 4 * (kMaxChunks + 2), 256);
     pl->ws_bytes = wsoff;
     *out = pl;
     return UAVQ_OK;

@@ -45,6 +45,8 @@ struct KArgs {
     const WorkItem *items;
     int32_t n_items;
     int32_t item_base;          // first item of this launch
+    int32_t *queue;             // persistent mode: item counter of this launch (NULL = one item per block)
+    int32_t queue_n;            // items in this launch (persistent mode)
     const uint32_t *thr;        // S rows of thr_stride entries (d = 0..Dmax used)
     int32_t thr_stride;         // multiple of 4
     const int32_t *dcut;        // S: least d with thr[s][d] == 0
@@ -102,9 +104,16 @@ struct uavq_plan {
     int32_t variant;                      // UAVQ_VARIANT_* (kernel choice; never changes results)
     int32_t timing = 0;                   // record events around the sweep launches
     void *ev[2 * (uavq::kMaxChunks + 1)] = {};
+    int32_t persistent = 0, graph = 0;
+    int32_t prepared = 0, cu_count = 0;
+    int32_t max_blocks[uavq::kMaxChunks + 2] = {};   // resident blocks per CU of each class's kernel
+    size_t lds_class[uavq::kMaxChunks + 2] = {};
+    size_t queue_off = 0;                 // workspace: item counters (persistent mode)
+    void *graph_exec = nullptr;           // cached hipGraphExec_t (graph mode)
+    uint64_t graph_key = 0;
 };
 
-extern "C" void plan_destroy_events(uavq_plan *pl);
+extern "C" void plan_destroy_events(uavq_plan *pl);   // also releases a cached graph
 
 // Kernel launchers (uavq_kernels.hip).
 namespace uavq {

@@ -29,6 +29,10 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
 
 #include "uavq_device.h"
 
@@ -132,11 +136,10 @@ struct Prefetch {
 };
 
 template <int NJ>
-__global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
+__device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *smem) {
     using Ops = RowOps<NJ>;
     constexpr int KP = Prefetch<NJ>::K;
-    const WorkItem it = a.items[a.item_base + blockIdx.x];
+    const WorkItem it = a.items[itx];
     const InstDesc d = a.desc[it.inst];
     const int m = d.m, W = d.row_words, twoP = 2 * d.P;
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
@@ -442,16 +445,38 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
     }
 }
 
+// Work-item loop: one item per block, or (persistent mode) items pulled in
+// order from a counter until the class is exhausted.
+__device__ __forceinline__ int next_item(const KArgs &a, int iter) {
+    __shared__ int s_item;
+    if (!a.queue) return iter == 0 ? a.item_base + (int)blockIdx.x : -1;
+    __syncthreads();
+    if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int k = s_item;
+    return k < a.queue_n ? a.item_base + k : -1;
+}
+
+template <int NJ>
+__global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int iter = 0;; iter++) {
+        const int itx = next_item(a, iter);
+        if (itx < 0) break;
+        factored_item<NJ>(a, itx, smem);
+    }
+}
+
+
 // ------------------------------------------------ sweep, LDS-resident rows --
 // Variant for m <= 64 (one cell per lane): lane c keeps its cell's column of
 // the state as a 64-bit step mask, and the travel rows Y_t (t = 1..m) are
 // kept in LDS (int16, one 64-entry row per step) and updated on accepts, so
 // that visiting a step costs one LDS read (issued a step ahead) and a ballot.
 // Same trajectory as k_sweep_factored bit for bit.
-__global__ __launch_bounds__(1024) void k_sweep_ylds(KArgs a) {
-    extern __shared__ __align__(16) uint8_t smem[];
+__device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem) {
     constexpr int KP = 6;
-    const WorkItem it = a.items[a.item_base + blockIdx.x];
+    const WorkItem it = a.items[itx];
     const InstDesc d = a.desc[it.inst];
     const int m = d.m, W = d.row_words, twoP = 2 * d.P;
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
@@ -665,6 +690,21 @@ __global__ __launch_bounds__(1024) void k_sweep_ylds(KArgs a) {
     }
 }
 
+__global__ __launch_bounds__(1024) void k_sweep_ylds(KArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int iter = 0;; iter++) {
+        const int itx = next_item(a, iter);
+        if (itx < 0) break;
+        ylds_item(a, itx, smem);
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+
 // ------------------------------------------------------------ reduction --
 // Per instance: lexicographic minimum of (best_E, replica), then copy of the
 // winner's best state.
@@ -710,51 +750,86 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a) {
 }
 
 // ------------------------------------------------------------- launchers --
-template <int NJ>
-static int launch_factored_class(const uavq_plan *pl, KArgs a, int cls, hipStream_t st) {
-    const int b0 = pl->class_begin[cls], b1 = pl->class_begin[cls + 1];
-    if (b1 <= b0) return UAVQ_OK;
-    int mmax = 0;
-    for (int i = b0; i < b1; i++) mmax = std::max(mmax, pl->desc[pl->items[i].inst].m);
-    const size_t lds = 8 * (size_t)pl->thr_stride + al16((size_t)mmax * mmax) + al16((size_t)mmax);
-    if (lds > 160 * 1024)
-        return set_error(UAVQ_ETOOBIG, "anneal: LDS need %zu bytes (m = %d, Dmax = %d)", lds, mmax, pl->Dmax);
-    UAVQ_HIP(hipFuncSetAttribute((const void *)k_sweep_factored<NJ>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds));
-    a.item_base = b0;
-    const int wpb = pl->waves_per_block[cls];
-    if (pl->timing) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls], st));
-    hipLaunchKernelGGL(k_sweep_factored<NJ>, dim3(b1 - b0), dim3(64 * wpb), lds, st, a);
-    if (pl->timing) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls + 1], st));
-    UAVQ_HIP(hipGetLastError());
-    return UAVQ_OK;
-}
-
 static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
     return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + (size_t)wpb * 64 * m * 2;
 }
 
-// chunk class 1 (m <= 64) with the LDS-resident travel rows
-static int launch_ylds_class(const uavq_plan *pl, KArgs a, hipStream_t st) {
-    const int b0 = pl->class_begin[1], b1 = pl->class_begin[2];
-    if (b1 <= b0) return UAVQ_OK;
+static size_t factored_lds_bytes(const uavq_plan *pl, int m) {
+    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m);
+}
+
+static int class_mmax(const uavq_plan *pl, int cls) {
     int mmax = 0;
-    for (int i = b0; i < b1; i++) mmax = std::max(mmax, pl->desc[pl->items[i].inst].m);
-    const int wpb = pl->waves_per_block[1];
-    const size_t lds = ylds_lds_bytes(pl, mmax, wpb);
-    UAVQ_HIP(hipFuncSetAttribute((const void *)k_sweep_ylds, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    a.item_base = b0;
-    if (pl->timing) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2], st));
-    hipLaunchKernelGGL(k_sweep_ylds, dim3(b1 - b0), dim3(64 * wpb), lds, st, a);
-    if (pl->timing) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[3], st));
-    UAVQ_HIP(hipGetLastError());
-    return UAVQ_OK;
+    for (int i = pl->class_begin[cls]; i < pl->class_begin[cls + 1]; i++)
+        mmax = std::max(mmax, pl->desc[pl->items[i].inst].m);
+    return mmax;
 }
 
 bool ylds_fits(const uavq_plan *pl) {
-    int mmax = 0;
-    for (int i = pl->class_begin[1]; i < pl->class_begin[2]; i++) mmax = std::max(mmax, pl->desc[pl->items[i].inst].m);
-    return ylds_lds_bytes(pl, mmax, pl->waves_per_block[1]) <= 160 * 1024;
+    return ylds_lds_bytes(pl, class_mmax(pl, 1), pl->waves_per_block[1]) <= 160 * 1024;
+}
+
+static bool use_ylds(const uavq_plan *pl) { return pl->variant != UAVQ_VARIANT_ROWMASK && ylds_fits(pl); }
+
+static const void *class_kernel(const uavq_plan *pl, int cls) {
+    if (cls == 1) return use_ylds(pl) ? (const void *)k_sweep_ylds : (const void *)k_sweep_factored<1>;
+    if (cls == 2) return (const void *)k_sweep_factored<2>;
+    return (const void *)k_sweep_factored<3>;
+}
+
+// Kernel attributes and occupancy, once per plan and outside any stream
+// capture: dynamic LDS limits and, for persistent launches, resident blocks.
+static int prepare(const uavq_plan *cpl) {
+    uavq_plan *pl = const_cast<uavq_plan *>(cpl);
+    if (pl->prepared) return UAVQ_OK;
+    int dev = 0;
+    UAVQ_HIP(hipGetDevice(&dev));
+    UAVQ_HIP(hipDeviceGetAttribute(&pl->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+    for (int cls = 1; cls <= kMaxChunks; cls++) {
+        if (pl->dense || pl->class_begin[cls + 1] <= pl->class_begin[cls]) continue;
+        const int mmax = class_mmax(pl, cls), wpb = pl->waves_per_block[cls];
+        const size_t lds = (cls == 1 && use_ylds(pl)) ? ylds_lds_bytes(pl, mmax, wpb) : factored_lds_bytes(pl, mmax);
+        if (lds > 160 * 1024)
+            return set_error(UAVQ_ETOOBIG, "anneal: LDS need %zu bytes (m = %d, Dmax = %d)", lds, mmax, pl->Dmax);
+        const void *k = class_kernel(pl, cls);
+        UAVQ_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+        int nb = 0;
+        UAVQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * wpb, lds));
+        pl->max_blocks[cls] = std::max(nb, 1);
+        pl->lds_class[cls] = lds;
+    }
+    pl->prepared = 1;
+    return UAVQ_OK;
+}
+
+static int launch_class(const uavq_plan *pl, KArgs a, int cls, hipStream_t st) {
+    const int b0 = pl->class_begin[cls], b1 = pl->class_begin[cls + 1];
+    if (b1 <= b0) return UAVQ_OK;
+    const int n = b1 - b0, wpb = pl->waves_per_block[cls];
+    a.item_base = b0;
+    int grid = n;
+    if (pl->persistent) {
+        a.queue = (int32_t *)(a.ws + pl->queue_off) + cls;
+        a.queue_n = n;
+        grid = std::min(n, pl->max_blocks[cls] * pl->cu_count);
+    } else {
+        a.queue = nullptr;
+        a.queue_n = 0;
+    }
+    const bool timed = pl->timing && !pl->graph;
+    if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls], st));
+    const size_t lds = pl->lds_class[cls];
+    if (cls == 1 && use_ylds(pl))
+        hipLaunchKernelGGL(k_sweep_ylds, dim3(grid), dim3(64 * wpb), lds, st, a);
+    else if (cls == 1)
+        hipLaunchKernelGGL(k_sweep_factored<1>, dim3(grid), dim3(64 * wpb), lds, st, a);
+    else if (cls == 2)
+        hipLaunchKernelGGL(k_sweep_factored<2>, dim3(grid), dim3(64 * wpb), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_sweep_factored<3>, dim3(grid), dim3(64 * wpb), lds, st, a);
+    UAVQ_HIP(hipGetLastError());
+    if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls + 1], st));
+    return UAVQ_OK;
 }
 
 // energies of the final states recomputed by the MFMA refresh (invariant check)
@@ -768,28 +843,28 @@ static int launch_checks(const uavq_plan *pl, const KArgs &a, int64_t *check_E, 
     return UAVQ_OK;
 }
 
+// init -> sweeps (one kernel per chunk class) -> reduce [-> energy check]
 int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *check_E) {
     hipStream_t st = (hipStream_t)stream;
     KArgs a = a0;
     const int n_items = (int)pl->items.size();
     if (n_items == 0) return UAVQ_OK;
     a.item_base = 0;
+    a.queue = nullptr;
     hipLaunchKernelGGL(k_init_states, dim3(n_items), dim3(256), 0, st, a);
     UAVQ_HIP(hipGetLastError());
     int rc;
     if (pl->dense) {
         if ((rc = launch_dense(pl, a, st))) return rc;
-        hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
-        UAVQ_HIP(hipGetLastError());
-        return check_E ? launch_checks(pl, a, check_E, st) : UAVQ_OK;
+    } else {
+        if (pl->persistent) {
+            // reset the item counters with a kernel (graph-safe, no memset node)
+            hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int32_t *)(a.ws + pl->queue_off), kMaxChunks + 2, 0);
+            UAVQ_HIP(hipGetLastError());
+        }
+        for (int cls = 1; cls <= kMaxChunks; cls++)
+            if ((rc = launch_class(pl, a, cls, st))) return rc;
     }
-    if (pl->variant != UAVQ_VARIANT_ROWMASK && ylds_fits(pl)) {
-        if ((rc = launch_ylds_class(pl, a, st))) return rc;
-    } else if ((rc = launch_factored_class<1>(pl, a, 1, st))) {
-        return rc;
-    }
-    if ((rc = launch_factored_class<2>(pl, a, 2, st))) return rc;
-    if ((rc = launch_factored_class<3>(pl, a, 3, st))) return rc;
     hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
     UAVQ_HIP(hipGetLastError());
     return check_E ? launch_checks(pl, a, check_E, st) : UAVQ_OK;
@@ -810,6 +885,19 @@ int launch_energy(const uavq_qubo *q, const uint32_t *d_x, int64_t n, int64_t *d
     return launch_energy_refresh(d_x, n, d_E, dD, ddep, q->m, q->P, q->closed, q->c0, st);
 }
 
+static uint64_t mix64(uint64_t h, uint64_t v) {
+    h ^= v + 0x9E3779B97F4A7C15ull + (h << 6) + (h >> 2);
+    return h;
+}
+
+static void release_graph(uavq_plan *pl) {
+    if (pl->graph_exec) {
+        (void)hipGraphExecDestroy((hipGraphExec_t)pl->graph_exec);
+        pl->graph_exec = nullptr;
+        pl->graph_key = 0;
+    }
+}
+
 }  // namespace uavq
 
 using namespace uavq;
@@ -819,6 +907,8 @@ extern "C" {
 int uavq_plan_upload(const uavq_plan *pl, void *d_ws, size_t ws_bytes, void *stream) {
     if (!pl || !d_ws) return set_error(UAVQ_EINVAL, "plan_upload: null argument");
     if (ws_bytes < pl->ws_bytes) return set_error(UAVQ_EINVAL, "plan_upload: workspace %zu < %zu bytes", ws_bytes, pl->ws_bytes);
+    int rc = prepare(pl);
+    if (rc) return rc;
     UAVQ_HIP(hipMemcpyAsync(d_ws, pl->blob.data(), pl->blob.size(), hipMemcpyHostToDevice, (hipStream_t)stream));
     return UAVQ_OK;
 }
@@ -833,6 +923,9 @@ int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const ua
         return set_error(UAVQ_EINVAL, "anneal_batch: a required output is NULL");
     if (init && init->seeded && !init->states)
         return set_error(UAVQ_EINVAL, "anneal_batch: seeded replicas need init->states");
+    if (pl->graph && !stream) return set_error(UAVQ_EINVAL, "anneal_batch: graph mode needs a non-default stream");
+    int rc = prepare(pl);
+    if (rc) return rc;
     KArgs a{};
     const uint8_t *ws = (const uint8_t *)d_ws;
     a.ws = ws;
@@ -865,7 +958,36 @@ int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const ua
     a.inst_best_sweep = out->inst_best_sweep;
     a.inst_best_state = out->inst_best_state;
     a.inst_state_off = (int64_t *)(ws + pl->inst_state_off_off);
-    return launch_anneal(pl, a, stream, out->check_E);
+    if (!pl->graph) return launch_anneal(pl, a, stream, out->check_E);
+
+    // graph mode: replay the captured sequence while every pointer is unchanged
+    uavq_plan *mp = const_cast<uavq_plan *>(pl);
+    uint64_t key = 0x12345678ull;
+    const void *ptrs[] = {d_ws, stream, a.init_states, a.seeded, a.start_sweep, out->final_states, out->final_E,
+                          out->best_E, out->best_sweep, out->best_states, out->accepts, out->draws, out->inst_best_E,
+                          out->inst_best_replica, out->inst_best_sweep, out->inst_best_state, out->check_E};
+    for (const void *p : ptrs) key = mix64(key, (uint64_t)(uintptr_t)p);
+    hipStream_t st = (hipStream_t)stream;
+    if (!mp->graph_exec || mp->graph_key != key) {
+        release_graph(mp);
+        UAVQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        rc = launch_anneal(pl, a, stream, out->check_E);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return set_error(UAVQ_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        hipGraphExec_t ge = nullptr;
+        e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return set_error(UAVQ_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        mp->graph_exec = (void *)ge;
+        mp->graph_key = key;
+    }
+    UAVQ_HIP(hipGraphLaunch((hipGraphExec_t)mp->graph_exec, st));
+    return UAVQ_OK;
 }
 
 int uavq_plan_set_timing(uavq_plan *pl, int32_t enable) {
@@ -883,7 +1005,7 @@ int uavq_plan_set_timing(uavq_plan *pl, int32_t enable) {
 
 int uavq_plan_sweep_ms(const uavq_plan *pl, float *ms) {
     if (!pl || !ms) return set_error(UAVQ_EINVAL, "plan_sweep_ms: null argument");
-    if (!pl->timing) return set_error(UAVQ_EINVAL, "plan_sweep_ms: timing not enabled");
+    if (!pl->timing || pl->graph) return set_error(UAVQ_EINVAL, "plan_sweep_ms: timing not enabled (or graph mode)");
     float total = 0.f;
     for (int cls = 1; cls <= kMaxChunks; cls++) {
         if (pl->class_begin[cls + 1] <= pl->class_begin[cls]) continue;
@@ -901,6 +1023,7 @@ void plan_destroy_events(uavq_plan *pl) {
             (void)hipEventDestroy((hipEvent_t)pl->ev[i]);
             pl->ev[i] = nullptr;
         }
+    release_graph(pl);
 }
 
 int uavq_energy_workspace_bytes(const uavq_qubo *q, size_t *bytes) {
@@ -914,6 +1037,167 @@ int uavq_energy_eval_dev(const uavq_qubo *q, const uint32_t *d_x, int64_t n, int
     if (!q || n < 0 || (n > 0 && (!d_x || !d_E))) return set_error(UAVQ_EINVAL, "energy_eval_dev: bad argument");
     if (n == 0) return UAVQ_OK;
     return launch_energy(q, d_x, n, d_E, d_ws, ws_bytes, stream);
+}
+
+// ------------------------------------------------------------- autotuner --
+// Candidate launch shapes are timed with HIP events on a trial plan of
+// trial_sweeps sweeps (same instances and replicas), using device memory
+// allocated here; the fastest is returned and optionally cached as JSON.
+static std::string tune_key(const uavq_qubo *const *q, int32_t n, const uavq_anneal_params *p, int cu) {
+    int mmax[kMaxChunks + 1] = {0}, cnt[kMaxChunks + 1] = {0};
+    for (int32_t i = 0; i < n; i++) {
+        const int c = std::min((q[i]->m + 63) / 64, kMaxChunks);
+        mmax[c] = std::max(mmax[c], q[i]->m);
+        cnt[c]++;
+    }
+    char buf[256];
+    int len = snprintf(buf, sizeof buf, "gfx950|cu%d|R%d|flags%u", cu, p->replicas,
+                       (unsigned)(p->flags & (UAVQ_PERSISTENT | UAVQ_KERNEL_DENSE)));
+    for (int c = 1; c <= kMaxChunks; c++)
+        if (cnt[c]) {
+            int lg = 0;
+            while ((1 << (lg + 1)) <= cnt[c]) lg++;
+            len += snprintf(buf + len, sizeof buf - len, "|c%d:m%d:n%d", c, (mmax[c] + 7) / 8 * 8, 1 << lg);
+        }
+    return std::string(buf);
+}
+
+static bool cache_lookup(const char *path, const std::string &key, uavq_tune *t) {
+    FILE *f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool found = false;
+    while (fgets(line, sizeof line, f)) {
+        char *q1 = strchr(line, '"');
+        if (!q1) continue;
+        char *q2 = strchr(q1 + 1, '"');
+        if (!q2) continue;
+        if (std::string(q1 + 1, q2) != key) continue;
+        uavq_tune v{};
+        unsigned var = 0;
+        if (sscanf(q2 + 1, ": {\"wpb\": [%d, %d, %d], \"variant\": %u, \"ms\": %f}", &v.waves_per_block[1],
+                   &v.waves_per_block[2], &v.waves_per_block[3], &var, &v.trial_ms) == 5) {
+            v.variant_flags = var;
+            *t = v;
+            found = true;
+        }
+    }
+    fclose(f);
+    return found;
+}
+
+static void cache_store(const char *path, const std::string &key, const uavq_tune &t) {
+    std::vector<std::string> keep;
+    if (FILE *f = fopen(path, "r")) {
+        char line[1024];
+        while (fgets(line, sizeof line, f)) {
+            char *q1 = strchr(line, '"');
+            if (!q1) continue;
+            char *q2 = strchr(q1 + 1, '"');
+            if (!q2 || std::string(q1 + 1, q2) == key) continue;
+            std::string l(line);
+            while (!l.empty() && (l.back() == '\n' || l.back() == ',')) l.pop_back();
+            keep.push_back(l);
+        }
+        fclose(f);
+    }
+    char buf[512];
+    snprintf(buf, sizeof buf, "\"%s\": {\"wpb\": [%d, %d, %d], \"variant\": %u, \"ms\": %.4f}", key.c_str(),
+             t.waves_per_block[1], t.waves_per_block[2], t.waves_per_block[3], (unsigned)t.variant_flags, t.trial_ms);
+    keep.push_back(buf);
+    std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "w");
+    if (!f) return;
+    fprintf(f, "{\n");
+    for (size_t i = 0; i < keep.size(); i++) fprintf(f, "%s%s\n", keep[i].c_str(), i + 1 < keep.size() ? "," : "");
+    fprintf(f, "}\n");
+    fclose(f);
+    rename(tmp.c_str(), path);
+}
+
+int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *inst_ids, const uavq_anneal_params *p,
+                  int32_t trial_sweeps, const char *cache_path, uavq_tune *out) {
+    if (!q || !inst_ids || !p || !out || n_inst < 1 || trial_sweeps < 1)
+        return set_error(UAVQ_EINVAL, "autotune: bad argument");
+    int dev = 0, cu = 0;
+    UAVQ_HIP(hipGetDevice(&dev));
+    UAVQ_HIP(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+    const std::string key = tune_key(q, n_inst, p, cu);
+    if (cache_path && cache_lookup(cache_path, key, out)) return UAVQ_OK;
+
+    const int wpbs[] = {1, 2, 4, 8, 16};
+    const uint32_t variants[] = {0u, UAVQ_VARIANT_ROWMASK};
+    hipStream_t st = nullptr;
+    UAVQ_HIP(hipStreamCreate(&st));
+    hipEvent_t e0, e1;
+    UAVQ_HIP(hipEventCreate(&e0));
+    UAVQ_HIP(hipEventCreate(&e1));
+    uavq_tune best{};
+    best.trial_ms = 1e30f;
+    int rc = UAVQ_OK;
+    for (uint32_t var : variants) {
+        for (int wpb : wpbs) {
+            uavq_tune t{};
+            for (int c = 1; c <= kMaxChunks; c++) t.waves_per_block[c] = wpb;
+            t.variant_flags = var;
+            uavq_anneal_params tp = *p;
+            tp.sweeps = trial_sweeps;
+            tp.flags &= ~(uint32_t)(UAVQ_GRAPH | UAVQ_VARIANT_ROWMASK);
+            tp.tune = &t;
+            uavq_plan *pl = nullptr;
+            if (uavq_plan_create(q, n_inst, inst_ids, &tp, &pl) != UAVQ_OK) continue;
+            void *ws = nullptr, *buf = nullptr;
+            const size_t R = (size_t)pl->total_rep, W = (size_t)pl->total_state_words;
+            size_t inst_words = 0;
+            for (int32_t i = 0; i < n_inst; i++) inst_words += (size_t)q[i]->m * q[i]->row_words;
+            const size_t nbuf = 2 * W * 4 + 6 * R * 8 + n_inst * 16 + inst_words * 4 + 1024;
+            bool ok = hipMalloc(&ws, pl->ws_bytes) == hipSuccess && hipMalloc(&buf, nbuf) == hipSuccess;
+            float ms = 1e30f;
+            if (ok && uavq_plan_upload(pl, ws, pl->ws_bytes, st) == UAVQ_OK) {
+                uint8_t *b = (uint8_t *)buf;
+                uavq_anneal_out o{};
+                o.final_states = (uint32_t *)b;            b += W * 4;
+                o.best_states = (uint32_t *)b;             b += W * 4;
+                b = (uint8_t *)(((uintptr_t)b + 255) & ~(uintptr_t)255);
+                o.final_E = (int64_t *)b;                  b += R * 8;
+                o.best_E = (int64_t *)b;                   b += R * 8;
+                o.accepts = (uint64_t *)b;                 b += R * 8;
+                o.draws = (uint64_t *)b;                   b += R * 8;
+                o.best_sweep = (int32_t *)b;               b += R * 8;
+                o.inst_best_E = (int64_t *)b;              b += (size_t)n_inst * 8;
+                o.inst_best_replica = (int32_t *)b;        b += (size_t)n_inst * 4;
+                o.inst_best_sweep = (int32_t *)b;          b += (size_t)n_inst * 4;
+                o.inst_best_state = (uint32_t *)b;
+                if (uavq_anneal_batch(pl, ws, pl->ws_bytes, nullptr, &o, st) == UAVQ_OK &&
+                    hipStreamSynchronize(st) == hipSuccess) {
+                    float acc[3];
+                    bool good = true;
+                    for (int rep = 0; rep < 3 && good; rep++) {
+                        good = hipEventRecord(e0, st) == hipSuccess &&
+                               uavq_anneal_batch(pl, ws, pl->ws_bytes, nullptr, &o, st) == UAVQ_OK &&
+                               hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+                               hipEventElapsedTime(&acc[rep], e0, e1) == hipSuccess;
+                    }
+                    if (good) ms = std::min(acc[0], std::min(acc[1], acc[2]));
+                }
+            }
+            (void)hipStreamSynchronize(st);
+            if (ws) (void)hipFree(ws);
+            if (buf) (void)hipFree(buf);
+            uavq_plan_free(pl);
+            if (ms < best.trial_ms) {
+                best = t;
+                best.trial_ms = ms;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipStreamDestroy(st);
+    if (best.trial_ms >= 1e30f) return set_error(UAVQ_EHIP, "autotune: no candidate ran");
+    *out = best;
+    if (cache_path) cache_store(cache_path, key, best);
+    return rc;
 }
 
 }  // extern "C"

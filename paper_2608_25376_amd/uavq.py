@@ -19,6 +19,8 @@ OPEN_PATH = 0x1
 DENSE = 0x2
 KERNEL_DENSE = 0x1
 VARIANT_ROWMASK = 0x10
+PERSISTENT = 0x20
+GRAPH = 0x40
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
 
@@ -41,9 +43,19 @@ class _QuboInfo(C.Structure):
                 ("state_words", C.c_int32)]
 
 
+class Tune(C.Structure):
+    """Launch shape chosen by autotune (per chunk class c = ceil(m/64))."""
+    _fields_ = [("waves_per_block", C.c_int32 * 4), ("variant_flags", C.c_uint32), ("trial_ms", C.c_float)]
+
+    def __repr__(self):
+        return (f"Tune(waves_per_block={list(self.waves_per_block)[1:]}, variant={self.variant_flags:#x}, "
+                f"trial_ms={self.trial_ms:.3f})")
+
+
 class _Params(C.Structure):
     _fields_ = [("replicas", C.c_int32), ("sweeps", C.c_int32), ("T0", C.c_double), ("T1", C.c_double),
-                ("seed", C.c_uint32), ("flags", C.c_uint32), ("waves_per_block", C.c_int32)]
+                ("seed", C.c_uint32), ("flags", C.c_uint32), ("waves_per_block", C.c_int32),
+                ("tune", C.POINTER(Tune))]
 
 
 class _PlanInfo(C.Structure):
@@ -66,7 +78,7 @@ EXPORTS = [
     "uavq_qubo_free_cells", "uavq_qubo_costs", "uavq_qubo_export", "uavq_energy_eval",
     "uavq_energy_workspace_bytes", "uavq_energy_eval_dev", "uavq_decode_path", "uavq_schedule",
     "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_layout", "uavq_plan_upload",
-    "uavq_anneal_batch", "uavq_plan_set_timing", "uavq_plan_sweep_ms",
+    "uavq_anneal_batch", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
 ]
 
 _lib = None
@@ -104,6 +116,7 @@ def lib():
         L.uavq_anneal_batch.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), vp]
         L.uavq_plan_set_timing.argtypes = [vp, C.c_int32]
         L.uavq_plan_sweep_ms.argtypes = [vp, P(C.c_float)]
+        L.uavq_autotune.argtypes = [P(vp), C.c_int32, P(C.c_uint32), P(_Params), C.c_int32, C.c_char_p, P(Tune)]
         _lib = L
     return _lib
 
@@ -266,14 +279,17 @@ class Plan:
 
     def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
                  T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
-                 rowmask: bool = False):
+                 rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None):
         self.qubos = list(qubos)
         n = len(self.qubos)
         arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in self.qubos])
         ids = np.ascontiguousarray(inst_ids, dtype=np.uint32)
         assert ids.size == n
         flags = (KERNEL_DENSE if dense else 0) | (VARIANT_ROWMASK if rowmask else 0)
-        p = _Params(replicas, sweeps, T0, T1, seed, flags, waves_per_block)
+        flags |= (PERSISTENT if persistent else 0) | (GRAPH if graph else 0)
+        self._tune = tune
+        p = _Params(replicas, sweeps, T0, T1, seed, flags, waves_per_block,
+                    C.pointer(tune) if tune is not None else None)
         h = C.c_void_p()
         _check(lib().uavq_plan_create(arr, n, _np_ptr(ids, C.c_uint32), C.byref(p), C.byref(h)))
         self._h = h
@@ -296,6 +312,8 @@ class Plan:
     def upload(self, device="cuda", stream=None):
         import torch
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
+        if stream is not None:
+            torch.cuda.synchronize()
         _check(lib().uavq_plan_upload(self._h, _dptr(self.ws), self.ws_bytes, _stream_handle(stream)))
         return self.ws
 
@@ -336,3 +354,16 @@ class Plan:
 
 def anneal_batch(plan: Plan, **kw) -> AnnealResult:
     return plan.anneal(**kw)
+
+
+def autotune(qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float, T1: float,
+             seed: int = 1, persistent: bool = False, trial_sweeps: int = 64, cache: Optional[str] = None) -> Tune:
+    """uavq_autotune: fastest launch shape for these instances (never changes results)."""
+    n = len(qubos)
+    arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in qubos])
+    ids = np.ascontiguousarray(inst_ids, dtype=np.uint32)
+    p = _Params(replicas, sweeps, T0, T1, seed, PERSISTENT if persistent else 0, 0, None)
+    t = Tune()
+    _check(lib().uavq_autotune(arr, n, _np_ptr(ids, C.c_uint32), C.byref(p), trial_sweeps,
+                               cache.encode() if cache else None, C.byref(t)))
+    return t

@@ -11,13 +11,14 @@ def say(msg):
 
 
 def gpu_anneal(U, grids, R, S, T0, T1, seed=1, dense=False, wpb=0, closed=True, init_x=None, seeded=None,
-               start_sweep=None, check_E=False, rowmask=False):
+               start_sweep=None, check_E=False, rowmask=False, persistent=False, graph=False, tune=None,
+               stream=None, replays=1):
     """Anneal ``grids`` (inputs.Grid list) on cuda:0; returns (qubos, plan, numpy results)."""
     import torch
     qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly, closed=closed, dense=dense) for g in grids]
     plan = U.Plan(qs, [g.inst_id for g in grids], R, S, T0, T1, seed, dense=dense, waves_per_block=wpb,
-                  rowmask=rowmask)
-    plan.upload()
+                  rowmask=rowmask, persistent=persistent, graph=graph, tune=tune)
+    plan.upload(stream=stream)
     kw = {}
     if init_x is not None:
         packed = np.concatenate([U.pack_states(init_x[i], q.m).reshape(-1) for i, q in enumerate(qs)])
@@ -27,7 +28,11 @@ def gpu_anneal(U, grids, R, S, T0, T1, seed=1, dense=False, wpb=0, closed=True, 
         kw["start_sweep"] = torch.from_numpy(np.ascontiguousarray(start_sweep, dtype=np.int32).reshape(-1)).cuda()
     if check_E:
         kw["check_E"] = torch.zeros(plan.total_replicas, dtype=torch.int64, device="cuda")
-    out = plan.anneal(**kw)
+    if stream is not None:
+        torch.cuda.synchronize()
+    out = plan.anneal(stream=stream, **kw)
+    for _ in range(replays - 1):
+        out = plan.anneal(out=out, stream=stream, **kw)
     torch.cuda.synchronize()
     res = {k: getattr(out, k).cpu().numpy() for k in out.__dataclass_fields__}
     if check_E:
