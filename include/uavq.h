@@ -229,6 +229,49 @@ int uavq_anneal_batch(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const 
 int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *inst_ids,
                   const uavq_anneal_params *p, int32_t trial_sweeps, const char *cache_path, uavq_tune *out);
 
+/* ------------------------------------------------------------ warm start -- */
+/* A per-cell network predicts, for every free cell, a distribution over the
+ * step at which a good tour visits it; tours sampled from it seed a fraction
+ * of the replicas, which then start at a later (colder) sweep.  Not in the
+ * paper: it is this project's learned warm start for the annealer of Alg. 1.
+ *
+ * Network: 16 inputs -> 128 -> 128 -> 128 logits (one per step; m <= 128),
+ * ReLU between layers, softmax over steps 1..m.  Parameters are one fp32
+ * vector of uavq_mlp_param_count() floats: W1[16][128], b1[128], W2[128][128],
+ * b2[128], W3[128][128], b3[128] (row-major, x W convention).  Every product
+ * rounds both operands to bfloat16 and accumulates in fp32 (MFMA).
+ * All pointers below are device pointers unless stated. */
+int uavq_mlp_param_count(void);
+/* Features (host): X[m][16] for the free cells in free-list order: (i, j)/(s-1);
+ * offset from the start cell /(s-1); its distance /(sqrt(2)(s-1)); no-fly
+ * cells at Chebyshev distance 1 (/8) and <= 2 (/24); for r = 1..8 the fraction
+ * of non-no-fly cells among the grid cells at Chebyshev distance r; m/99
+ * (s = max(rows, cols)). */
+int uavq_mlp_features(const uavq_qubo *q, float *X);
+/* Workspace for rows input rows (both calls below). */
+int uavq_mlp_workspace_bytes(int32_t rows, size_t *bytes);
+/* probs[rows][128]: softmax over the first m[row] steps (0 beyond). */
+int uavq_mlp_forward(const float *d_params, const float *d_X, const int32_t *d_m, int32_t rows, float *d_probs,
+                     void *d_ws, size_t ws_bytes, void *stream);
+/* Mean cross-entropy of the label steps (0-based, < m) and its gradient
+ * d_grad[param_count]; d_loss[0] = summed (not averaged) loss. */
+int uavq_mlp_loss_grad(const float *d_params, const float *d_X, const int32_t *d_m, const int32_t *d_label,
+                       int32_t rows, float *d_grad, float *d_loss, void *d_ws, size_t ws_bytes, void *stream);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected; step >= 1). */
+int uavq_mlp_adam(float *d_params, float *d_m1, float *d_m2, const float *d_grad, int32_t step, float lr,
+                  void *stream);
+/* q[row][t] = floor(p * 65534) + 1 (1..65535) for t < m[row], else 0 (uint16). */
+int uavq_quantize_marginals(const float *d_probs, const int32_t *d_m, int32_t rows, uint16_t *d_q, void *stream);
+/* Seed states: for instance i of the plan, replicas 0..n_seeded[i]-1 get a
+ * permutation drawn from q (rows q_row_off[i] .. +m of 128 steps), written to
+ * d_states in the plan's state layout.  Step t goes to the first unvisited
+ * cell whose running sum of q[., t] over unvisited cells exceeds
+ * floor(u W / 2^32), u = word 0 of Philox({t, r, id, 0}, {seed, 4}).
+ * q_row_off and n_seeded are host arrays; d_scratch holds 32 bytes per
+ * instance.  Synchronises the stream before returning. */
+int uavq_sample_seeds(const uavq_plan *plan, const uint16_t *d_q, const int64_t *q_row_off, const int32_t *n_seeded,
+                      uint32_t *d_states, void *d_scratch, size_t scratch_bytes, void *stream);
+
 /* Kernel timing for measurement: when enabled, uavq_anneal_batch records HIP
  * events on its stream around the sweep-kernel launches of this plan, and
  * uavq_plan_sweep_ms returns their elapsed time (ms) for the last call once

@@ -478,3 +478,37 @@ int64_t orc_held_karp(int32_t m, const int32_t *W, int32_t closed)
     free(dp);
     return best;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Warm-start seed sampler (integer).  For t = 1..m: W = sum over unvisited  */
+/* cells of q[c][t-1]; u = word 0 of Philox({t, r, inst, 0}, {seed, 4});     */
+/* target = floor(u W / 2^32); step t goes to the first unvisited cell (in   */
+/* free-list order) whose running sum of weights exceeds the target.         */
+/* q is m rows (cells) of 128 steps; x receives the m x m permutation state. */
+/* ------------------------------------------------------------------------ */
+int32_t orc_sample_seed(int32_t m, const uint16_t *q, uint32_t seed, uint32_t inst, uint32_t r, uint8_t *x)
+{
+    uint8_t used[256];
+    if (m < 1 || m > 128) return -1;
+    memset(used, 0, sizeof used);
+    memset(x, 0, (size_t)m * m);
+    for (int32_t t = 1; t <= m; t++) {
+        uint64_t W = 0;
+        for (int32_t c = 0; c < m; c++)
+            if (!used[c]) W += q[c * 128 + (t - 1)];
+        uint32_t ctr[4] = { (uint32_t)t, r, inst, 0u }, key[2] = { seed, 4u }, out[4];
+        orc_philox4x32_10(ctr, key, out);
+        uint64_t target = ((uint64_t)out[0] * W) >> 32;
+        uint64_t run = 0;
+        int32_t pick = -1;
+        for (int32_t c = 0; c < m; c++) {
+            if (used[c]) continue;
+            run += q[c * 128 + (t - 1)];
+            if (run > target) { pick = c; break; }
+        }
+        if (pick < 0) return -2;
+        used[pick] = 1;
+        x[(t - 1) * m + pick] = 1;
+    }
+    return 0;
+}

@@ -249,6 +249,44 @@ int uavq_decode_path(const uavq_qubo *q, const uint32_t *x, int32_t *path, int64
     return UAVQ_OK;
 }
 
+// Per-cell features of the warm-start network (16 per free cell, free-list order).
+int uavq_mlp_features(const uavq_qubo *q, float *X) {
+    if (!q || !X) return set_error(UAVQ_EINVAL, "mlp_features: null argument");
+    const int32_t R = q->rows, Cn = q->cols, m = q->m;
+    std::vector<uint8_t> freecell((size_t)R * Cn, 0);
+    freecell[q->depot] = 1;
+    for (int32_t g : q->F) freecell[g] = 1;
+    const int32_t side = std::max(R, Cn);
+    const double den = side > 1 ? (double)(side - 1) : 1.0;
+    const int32_t i0 = q->depot / Cn, j0 = q->depot % Cn;
+    for (int32_t c = 0; c < m; c++) {
+        const int32_t i = q->F[c] / Cn, j = q->F[c] % Cn;
+        float *f = X + (size_t)c * 16;
+        f[0] = (float)(i / den);
+        f[1] = (float)(j / den);
+        f[2] = (float)((i - i0) / den);
+        f[3] = (float)((j - j0) / den);
+        f[4] = (float)(std::sqrt((double)(i - i0) * (i - i0) + (double)(j - j0) * (j - j0)) / (std::sqrt(2.0) * den));
+        int nf1 = 0, nf2 = 0;
+        int ring_free[9] = {0}, ring_all[9] = {0};
+        for (int32_t a = 0; a < R; a++)
+            for (int32_t b = 0; b < Cn; b++) {
+                const int32_t d = std::max(std::abs(a - i), std::abs(b - j));
+                if (d == 0 || d > 8) continue;
+                const bool fr = freecell[(size_t)a * Cn + b] != 0;
+                if (!fr && d == 1) nf1++;
+                if (!fr && d <= 2) nf2++;
+                ring_all[d]++;
+                if (fr) ring_free[d]++;
+            }
+        f[5] = (float)(nf1 / 8.0);
+        f[6] = (float)(nf2 / 24.0);
+        for (int r = 1; r <= 8; r++) f[6 + r] = ring_all[r] ? (float)((double)ring_free[r] / ring_all[r]) : 0.0f;
+        f[15] = (float)(m / 99.0);
+    }
+    return UAVQ_OK;
+}
+
 int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr) {
     if (!Dmax || S < 1 || !(T1 > 0.0) || !(T1 <= T0) || !std::isfinite(T0) || T0 > 1e7)
         return set_error(UAVQ_EINVAL, "schedule: need S >= 1 and 0 < T1 <= T0 (finite)");

@@ -79,6 +79,8 @@ EXPORTS = [
     "uavq_energy_workspace_bytes", "uavq_energy_eval_dev", "uavq_decode_path", "uavq_schedule",
     "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_layout", "uavq_plan_upload",
     "uavq_anneal_batch", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
+    "uavq_mlp_param_count", "uavq_mlp_features", "uavq_mlp_workspace_bytes", "uavq_mlp_forward",
+    "uavq_mlp_loss_grad", "uavq_mlp_adam", "uavq_quantize_marginals", "uavq_sample_seeds",
 ]
 
 _lib = None
@@ -117,6 +119,14 @@ def lib():
         L.uavq_plan_set_timing.argtypes = [vp, C.c_int32]
         L.uavq_plan_sweep_ms.argtypes = [vp, P(C.c_float)]
         L.uavq_autotune.argtypes = [P(vp), C.c_int32, P(C.c_uint32), P(_Params), C.c_int32, C.c_char_p, P(Tune)]
+        L.uavq_mlp_param_count.restype = C.c_int
+        L.uavq_mlp_features.argtypes = [vp, P(C.c_float)]
+        L.uavq_mlp_workspace_bytes.argtypes = [C.c_int32, P(C.c_size_t)]
+        L.uavq_mlp_forward.argtypes = [vp, vp, vp, C.c_int32, vp, vp, C.c_size_t, vp]
+        L.uavq_mlp_loss_grad.argtypes = [vp, vp, vp, vp, C.c_int32, vp, vp, vp, C.c_size_t, vp]
+        L.uavq_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, vp]
+        L.uavq_quantize_marginals.argtypes = [vp, vp, C.c_int32, vp, vp]
+        L.uavq_sample_seeds.argtypes = [vp, vp, P(C.c_int64), P(C.c_int32), vp, vp, C.c_size_t, vp]
         _lib = L
     return _lib
 
@@ -367,3 +377,85 @@ def autotune(qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, swee
     _check(lib().uavq_autotune(arr, n, _np_ptr(ids, C.c_uint32), C.byref(p), trial_sweeps,
                                cache.encode() if cache else None, C.byref(t)))
     return t
+
+
+# ------------------------------------------------------------ warm start ----
+def mlp_param_count() -> int:
+    return int(lib().uavq_mlp_param_count())
+
+
+def mlp_features(q: Qubo) -> np.ndarray:
+    X = np.zeros((q.m, 16), np.float32)
+    _check(lib().uavq_mlp_features(q.handle, _np_ptr(X, C.c_float)))
+    return X
+
+
+class Mlp:
+    """Parameters (fp32 master, device), Adam moments and the step counter of
+    the warm-start network; every computation runs in the library's kernels."""
+
+    def __init__(self, params, device="cuda"):
+        import torch
+        p = torch.as_tensor(np.asarray(params, np.float32)).to(device)
+        assert p.numel() == mlp_param_count()
+        self.params = p.contiguous()
+        self.m1 = torch.zeros_like(self.params)
+        self.m2 = torch.zeros_like(self.params)
+        self.grad = torch.zeros_like(self.params)
+        self.loss = torch.zeros(1, dtype=torch.float32, device=device)
+        self.step_count = 0
+        self._ws = None
+
+    def _workspace(self, rows, device):
+        import torch
+        nb = C.c_size_t()
+        _check(lib().uavq_mlp_workspace_bytes(rows, C.byref(nb)))
+        if self._ws is None or self._ws.numel() < nb.value:
+            self._ws = torch.empty(nb.value, dtype=torch.uint8, device=device)
+        return self._ws, nb.value
+
+    def forward(self, X, msteps, stream=None):
+        import torch
+        rows = X.shape[0]
+        probs = torch.empty((rows, 128), dtype=torch.float32, device=X.device)
+        ws, nb = self._workspace(rows, X.device)
+        _check(lib().uavq_mlp_forward(_dptr(self.params), _dptr(X), _dptr(msteps), rows, _dptr(probs), _dptr(ws), nb,
+                                      _stream_handle(stream)))
+        return probs
+
+    def loss_grad(self, X, msteps, labels, stream=None):
+        rows = X.shape[0]
+        ws, nb = self._workspace(rows, X.device)
+        _check(lib().uavq_mlp_loss_grad(_dptr(self.params), _dptr(X), _dptr(msteps), _dptr(labels), rows,
+                                        _dptr(self.grad), _dptr(self.loss), _dptr(ws), nb, _stream_handle(stream)))
+        return self.loss, self.grad
+
+    def adam(self, lr=1e-3, stream=None):
+        self.step_count += 1
+        _check(lib().uavq_mlp_adam(_dptr(self.params), _dptr(self.m1), _dptr(self.m2), _dptr(self.grad),
+                                   self.step_count, lr, _stream_handle(stream)))
+
+    def train_step(self, X, msteps, labels, lr=1e-3, stream=None):
+        loss, _ = self.loss_grad(X, msteps, labels, stream)
+        self.adam(lr, stream)
+        return loss
+
+
+def quantize_marginals(probs, msteps, stream=None):
+    import torch
+    rows = probs.shape[0]
+    q = torch.empty((rows, 128), dtype=torch.int16, device=probs.device)
+    _check(lib().uavq_quantize_marginals(_dptr(probs), _dptr(msteps), rows, _dptr(q), _stream_handle(stream)))
+    return q
+
+
+def sample_seeds(plan: "Plan", q, q_row_off, n_seeded, states, stream=None):
+    """Write sampled permutations for replicas 0..n_seeded[i]-1 of every
+    instance into ``states`` (plan layout)."""
+    import torch
+    qo = np.ascontiguousarray(q_row_off, dtype=np.int64)
+    ns = np.ascontiguousarray(n_seeded, dtype=np.int32)
+    scratch = torch.empty(32 * max(len(ns), 1) + 64, dtype=torch.uint8, device=q.device)
+    torch.cuda.synchronize()
+    _check(lib().uavq_sample_seeds(plan._h, _dptr(q), _np_ptr(qo, C.c_int64), _np_ptr(ns, C.c_int32), _dptr(states),
+                                   _dptr(scratch), scratch.numel(), _stream_handle(stream)))

@@ -134,3 +134,15 @@ def test_plan_layout(U):
     assert p.ws_bytes > 0 and p.Dmax == U.schedule(50.0, 0.5, 20, table=False)[0]
     empty = U.Plan([], [], 4, 10, 10.0, 1.0)
     assert empty.total_replicas == 0
+
+
+def test_features_match_oracle(U, oracle_lib):
+    from oracle import mlp
+    for side, dens, inst in [(3, 0.0, 0), (10, 0.2, 1), (10, 0.1, 2), (6, 0.3, 3), (12, 0.05, 4)]:
+        g = inputs.grid(side, side, dens, seed=4, inst=inst)
+        q = U.qubo_build(side, side, nofly=g.nofly)
+        X = U.mlp_features(q)
+        Xo = mlp.features(side, side, 0, g.nofly)
+        assert X.shape == (q.m, 16)
+        assert np.abs(X - Xo).max() <= 1e-7
+    assert U.mlp_param_count() == mlp.N_PARAMS
