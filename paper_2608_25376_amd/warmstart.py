@@ -1,0 +1,281 @@
+"""Learned warm start: labelling, training and the time-to-target protocol.
+
+Driver only: every numeric step (annealing, features aside, network
+forward/backward/Adam, quantisation, sampling) runs in libuavq's kernels;
+this module moves tensors between those calls.
+
+Protocol (all inputs synthetic, 10x10 fields, no-fly density U[0, 0.2]):
+  1. label: anneal the training instances (ids from 10000) and take each
+     instance's best tour, oriented so that its first visited cell has the
+     smaller free-list index (a tour and its reversal cost the same);
+  2. train the per-cell network to predict the visiting step of every cell;
+  3. time-to-target on held-out instances (ids from 20000): the smallest
+     sweep budget S of a ladder at which the best energy is within 1% of the
+     best known energy (100 E <= 101 E_best_known), for
+       plain   - one launch per instance, all replicas random,
+       batched - all instances in one persistent launch,
+       warm    - half of the replicas seeded with tours sampled from the
+                 network and started at the first sweep with T_s <= T_warm,
+       batched+warm.
+     Warm times include feature, inference and sampling time.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2608_25376_amd import inputs, uavq  # noqa: E402
+
+
+def make_instances(n, first_id, seed=1, side=10, density_hi=0.2):
+    return inputs.batch(n, seed=seed, side=side, density_hi=density_hi, first_id=first_id)
+
+
+def _qubos(grids):
+    return [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in grids]
+
+
+def _anneal(qs, grids, R, S, T0, T1, seed, init=None, stream=None, out=None, plan=None):
+    """One persistent launch; returns (plan, out, elapsed ms)."""
+    import torch
+    if plan is None:
+        plan = uavq.Plan(qs, [g.inst_id for g in grids], R, S, T0, T1, seed, persistent=True)
+        plan.upload()
+    if out is None:
+        out = plan.alloc_outputs()
+    torch.cuda.synchronize()
+    s = stream or torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    plan.anneal(out=out, stream=s, **(init or {}))
+    e1.record(s)
+    torch.cuda.synchronize()
+    return plan, out, e0.elapsed_time(e1)
+
+
+def best_tours(plan, qs, out):
+    """Per instance: best energy and the visiting order (free-list indices) or None."""
+    E = out.inst_best_E.cpu().numpy()
+    words = out.inst_best_state.cpu().numpy().view(np.uint32)
+    res, off = [], 0
+    for i, q in enumerate(qs):
+        x = uavq.unpack_states(words[off:off + q.state_words], q.m).reshape(q.m, q.m)
+        off += q.state_words
+        order = None
+        if (x.sum(0) == 1).all() and (x.sum(1) == 1).all():
+            order = np.argmax(x, 1)
+        res.append((int(E[i]), order))
+    return res
+
+
+def canonical(order):
+    return order if order[0] < order[-1] else order[::-1]
+
+
+def label_data(grids, R, S, T0, T1, seed):
+    qs = _qubos(grids)
+    plan, out, ms = _anneal(qs, grids, R, S, T0, T1, seed)
+    data = []
+    for (E, order), q in zip(best_tours(plan, qs, out), qs):
+        if order is None:
+            continue
+        order = canonical(order)
+        labels = np.empty(q.m, np.int32)
+        labels[order] = np.arange(q.m, dtype=np.int32)     # cell -> step (0-based)
+        data.append((uavq.mlp_features(q), labels, q.m))
+    return data, ms
+
+
+def init_params(seed):
+    rng = np.random.default_rng(seed)
+    parts = [rng.uniform(-1, 1, (16, 128)) * np.sqrt(6 / (16 + 128)), np.zeros(128),
+             rng.uniform(-1, 1, (128, 128)) * np.sqrt(6 / 256), np.zeros(128),
+             rng.uniform(-1, 1, (128, 128)) * np.sqrt(6 / 256), np.zeros(128)]
+    return np.concatenate([p.reshape(-1) for p in parts]).astype(np.float32)
+
+
+def train(data, epochs=30, batch=64, lr=1e-3, seed=1, log=None):
+    import torch
+    net = uavq.Mlp(init_params(seed))
+    rng = np.random.default_rng(seed)
+    curve = []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        idx = rng.permutation(len(data))
+        tot, rows = 0.0, 0
+        for b in range(0, len(idx), batch):
+            sel = [data[i] for i in idx[b:b + batch]]
+            X = torch.from_numpy(np.concatenate([d[0] for d in sel])).cuda()
+            lab = torch.from_numpy(np.concatenate([d[1] for d in sel])).cuda()
+            msteps = torch.from_numpy(np.concatenate([np.full(d[2], d[2], np.int32) for d in sel])).cuda()
+            loss = net.train_step(X, msteps, lab, lr=lr)
+            tot += float(loss.cpu()[0])
+            rows += X.shape[0]
+        curve.append(tot / rows)
+        if log:
+            log(f"epoch {ep}: mean CE {curve[-1]:.4f}")
+    torch.cuda.synchronize()
+    return net, curve, time.perf_counter() - t0
+
+
+def first_sweep_below(T0, T1, S, T_warm):
+    """First s with T_s <= T_warm on the geometric schedule (the library's)."""
+    if S <= 1 or T_warm >= T0:
+        return 0
+    for s in range(S):
+        if T0 * (T1 / T0) ** (s / (S - 1)) <= T_warm:
+            return s
+    return S - 1
+
+
+def warm_init(net, plan, qs, frac, s0, stream=None):
+    """Seed states (first frac of each instance's replicas), seeded mask and
+    start sweeps; returns the init dict and the elapsed time (ms)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    X = torch.from_numpy(np.concatenate([uavq.mlp_features(q) for q in qs])).cuda()
+    msteps = torch.from_numpy(np.concatenate([np.full(q.m, q.m, np.int32) for q in qs])).cuda()
+    probs = net.forward(X, msteps)
+    qm = uavq.quantize_marginals(probs, msteps)
+    offs = np.cumsum([0] + [q.m for q in qs])[:-1]
+    R = plan.replicas
+    ns = [int(round(frac * R))] * len(qs)
+    states = torch.zeros(plan.total_state_words, dtype=torch.int32, device="cuda")
+    uavq.sample_seeds(plan, qm, offs, ns, states)
+    seeded = np.zeros(plan.total_replicas, np.uint8)
+    start = np.zeros(plan.total_replicas, np.int32)
+    for i in range(len(qs)):
+        r0 = plan.rep_offset[i]
+        seeded[r0:r0 + ns[i]] = 1
+        start[r0:r0 + ns[i]] = s0
+    init = {"init_states": states, "seeded": torch.from_numpy(seeded).cuda(),
+            "start_sweep": torch.from_numpy(start).cuda()}
+    torch.cuda.synchronize()
+    return init, (time.perf_counter() - t0) * 1e3
+
+
+def ttt(grids, net, R, ladder, T0, T1, seed, T_warm, frac=0.5, ref_sweeps=8000, single=True, log=None):
+    qs = _qubos(grids)
+    n = len(qs)
+    runs = {}            # (mode, S) -> (per-instance best E, ms)
+    # reference run (best known)
+    _, out, ms = _anneal(qs, grids, R, ref_sweeps, T0, T1, seed + 1000)
+    best_known = out.inst_best_E.cpu().numpy().copy()
+    for S in ladder:
+        s0 = first_sweep_below(T0, T1, S, T_warm)
+        plan, out, ms = _anneal(qs, grids, R, S, T0, T1, seed)
+        runs[("batched", S)] = (out.inst_best_E.cpu().numpy().copy(), ms)
+        init, inf_ms = warm_init(net, plan, qs, frac, s0)
+        plan, out, ms = _anneal(qs, grids, R, S, T0, T1, seed, init=init, plan=plan)
+        runs[("batched+warm", S)] = (out.inst_best_E.cpu().numpy().copy(), ms + inf_ms)
+        if single:
+            Ep, tp, Ew, tw = np.zeros(n, np.int64), np.zeros(n), np.zeros(n, np.int64), np.zeros(n)
+            for i in range(n):
+                p1, o1, m1 = _anneal([qs[i]], [grids[i]], R, S, T0, T1, seed)
+                Ep[i], tp[i] = int(o1.inst_best_E.cpu()[0]), m1
+                init, inf_ms = warm_init(net, p1, [qs[i]], frac, s0)
+                p1, o1, m1 = _anneal([qs[i]], [grids[i]], R, S, T0, T1, seed, init=init, plan=p1)
+                Ew[i], tw[i] = int(o1.inst_best_E.cpu()[0]), m1 + inf_ms
+            runs[("plain", S)] = (Ep, tp)
+            runs[("warm", S)] = (Ew, tw)
+        if log:
+            log(f"S={S}: " + ", ".join(f"{k[0]} {np.mean(100 * v[0] <= 101 * np.minimum(best_known, v[0])):.2f}"
+                                       for k, v in runs.items() if k[1] == S))
+    for v in runs.values():
+        best_known = np.minimum(best_known, v[0])
+    hit = lambda E: 100 * E <= 101 * best_known
+    report = {"instances": n, "replicas": R, "ladder": list(ladder), "T_warm": T_warm, "seeded_fraction": frac,
+              "modes": {}}
+    for mode in ("plain", "warm", "batched", "batched+warm"):
+        if (mode, ladder[0]) not in runs:
+            continue
+        frac_hit = {S: float(hit(runs[(mode, S)][0]).mean()) for S in ladder}
+        gap = {S: float(np.mean(runs[(mode, S)][0] / best_known - 1.0)) for S in ladder}
+        if mode in ("plain", "warm"):
+            # each instance stops at its own first budget at target (unsolved: the largest budget)
+            per = []
+            for i in range(n):
+                S_i = next((S for S in ladder if hit(runs[(mode, S)][0])[i]), None)
+                per.append((S_i is not None, float(runs[(mode, S_i if S_i is not None else ladder[-1])][1][i])))
+            solved = sum(ok for ok, _ in per)
+            report["modes"][mode] = {"ttt_ms": sum(t for _, t in per), "solved": solved,
+                                     "fraction_at_target": frac_hit, "mean_gap": gap}
+        else:
+            q = {}
+            for level in (0.5, 0.9, 1.0):
+                S_q = next((S for S in ladder if hit(runs[(mode, S)][0]).mean() >= level - 1e-12), None)
+                q[str(level)] = {"sweeps": S_q, "ms": runs[(mode, S_q)][1] if S_q is not None else None}
+            # the batched ladder yields every instance's first budget at target once it has run up to
+            # the largest such budget (the energies equal the per-instance launches: same instance ids)
+            firsts = [next((S for S in ladder if hit(runs[(mode, S)][0])[i]), None) for i in range(n)]
+            reached = [S for S in firsts if S is not None]
+            s_last = max(reached) if reached else None
+            ladder_ms = sum(runs[(mode, S)][1] for S in ladder if s_last is not None and S <= s_last)
+            report["modes"][mode] = {"ttt_ms": q["1.0"]["ms"], "ttt_quantiles": q, "fraction_at_target": frac_hit,
+                                     "mean_gap": gap, "ms_per_S": {S: runs[(mode, S)][1] for S in ladder},
+                                     "ladder_ms_to_all_first_hits": ladder_ms, "solved": len(reached)}
+    return report
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--train-n", type=int, default=2000)
+    ap.add_argument("--heldout-n", type=int, default=200)
+    ap.add_argument("--label-replicas", type=int, default=256)
+    ap.add_argument("--label-sweeps", type=int, default=2000)
+    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--lr", type=float, default=3e-3)
+    ap.add_argument("--batch", type=int, default=32)
+    ap.add_argument("--ladder", default="50,100,200,400,800,1600,3200")
+    ap.add_argument("--ref-sweeps", type=int, default=8000)
+    ap.add_argument("--T-warm", type=float, default=0.0, help="0 = choose on training instances")
+    ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available()
+    log = lambda s: print(s, flush=True)
+    T0, T1, seed = 200.0, 0.5, 1
+    train_grids = make_instances(args.train_n, 10000)
+    data, label_ms = label_data(train_grids, args.label_replicas, args.label_sweeps, T0, T1, seed)
+    log(f"labelled {len(data)}/{len(train_grids)} training instances in {label_ms / 1e3:.1f} s")
+    net, curve, train_s = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    ladder = [int(v) for v in args.ladder.split(",")]
+    T_warm = args.T_warm
+    if T_warm <= 0:
+        # choose on a slice of the training instances only
+        tune = make_instances(24, 10000)
+        best = None
+        for cand in (10.0, 25.0, 50.0, 100.0):
+            r = ttt(tune, net, args.replicas, [ladder[len(ladder) // 2]], T0, T1, seed + 7, cand,
+                    ref_sweeps=args.ref_sweeps // 2, single=False)
+            g = r["modes"]["batched+warm"]["mean_gap"][ladder[len(ladder) // 2]]
+            log(f"T_warm {cand}: mean gap {g:.4f}")
+            if best is None or g < best[0]:
+                best = (g, cand)
+        T_warm = best[1]
+    held = make_instances(args.heldout_n, 20000)
+    rep = ttt(held, net, args.replicas, ladder, T0, T1, seed, T_warm, ref_sweeps=args.ref_sweeps,
+              single=not args.no_single, log=log)
+    rep.update({"train_instances": len(data), "label_replicas": args.label_replicas,
+                "label_sweeps": args.label_sweeps, "label_s": label_ms / 1e3, "train_s": train_s,
+                "train_curve": curve, "epochs": args.epochs})
+    txt = json.dumps(rep)
+    print(txt, flush=True)
+    if args.out:
+        with open(args.out, "w") as f:
+            f.write(txt + "\n")
+        np.save(os.path.splitext(args.out)[0] + "_params.npy", net.params.cpu().numpy())
+
+
+if __name__ == "__main__":
+    main()
