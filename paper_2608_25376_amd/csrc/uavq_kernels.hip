@@ -488,7 +488,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     uint8_t *sD = smem + 8 * (size_t)Ts;
     uint8_t *sdep = sD + al16((size_t)m * m);
     uint16_t *Yall = reinterpret_cast<uint16_t *>(sdep + al16((size_t)m));
-    uint16_t *Yw = Yall + (size_t)wave * 64 * m;   // Y_t[c] at Yw[(t-1)*64 + c]
+    uint16_t *Yw = Yall + (size_t)wave * 64 * (m + 8);   // Y_t[c] at Yw[(t-1)*64 + c], t = 1..m+8
     __shared__ int s_first_sh;
     (void)nwaves;
 
@@ -559,11 +559,15 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         }
         lane_e += (int64_t)d.P * Cc * (Cc - 1);
         E = d.c0 + rowterm + wave_sum64(lane_e);
+        // boundary rows: step m+1 is the return leg (start-cell costs, or 0 for
+        // an open path), steps beyond it are zero; reads past m need no test
+        for (int t = m + 1; t <= m + 8; t++) Yw[(t - 1) * 64 + L] = (uint16_t)(t == m + 1 && d.closed ? dep : 0);
     }
 
     int64_t bestE = LLONG_MAX;
     int bestS = -1;
     uint64_t bestcm = cm;
+    int Kc = twoP * (Cc - 1);   // 2P (C_c - 1): the cell-count part of the field
     uint64_t nacc = 0, ndraw = 0;
     const int closed_dep = d.closed ? dep : 0;
 
@@ -580,66 +584,144 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         const uint32_t *thr = sthr + (s & 1) * Ts;
         const int dcut = uniform_load(a.dcut, s);
         if (active && s >= s0) {
-            int Yp = dep;
-            int Yc = Yw[L];
-            int Yn = m >= 2 ? (int)Yw[64 + L] : closed_dep;
-            int blk = -1;
-            uint4 u4 = make_uint4(0u, 0u, 0u, 0u);
-            for (int t = 1; t <= m; t++) {
-                // travel row of step t+2 (read a step ahead)
-                const int Ynn = (t + 2 <= m) ? (int)Yw[(t + 1) * 64 + L] : closed_dep;
-                const int xb = (int)((cm >> (t - 1)) & 1ull);
-                uint64_t rmask = ballot64(xb != 0);
-                int R = __popcll(rmask);
-                const int negx = -xb;
-                const int base = Yp + Yn + twoP * (Cc - 2 * xb - 1);
-                uint64_t open = lanes_m;
-                bool changed = false;
-                while (true) {
-                    const int h = base + twoP * R;
-                    const int dE = (h ^ negx) - negx;
-                    const bool mine = (open >> L) & 1ull;
-                    uint64_t accm = ballot64(mine && dE <= 0);
-                    const bool need = mine && dE > 0 && dE < dcut;
-                    const uint64_t needm = ballot64(need);
-                    if (needm) {
-                        const int tb = (t - 1) >> 2;
-                        if (blk != tb) {
-                            uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)tb;
+            // Steps are visited in blocks of four (the Philox blocks); Yv[k] holds
+            // Y_{t0-1+k} for the block starting at step t0, and the travel rows of
+            // the next block are prefetched from LDS while this one is processed.
+            int Yv0 = dep;                       // Y_{t0-1}, final
+            int Yv1 = Yw[L];                     // Y_{t0}
+            int pf[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) pf[k] = Yw[(1 + k) * 64 + L];   // steps 2..5 (padded)
+            uint32_t nacc_s = 0, ndraw_s = 0;
+            bool spec = true;
+            for (int t0 = 1; t0 <= m; t0 += 4) {
+                int Yv[6];
+                Yv[0] = Yv0;
+                Yv[1] = Yv1;
+#pragma unroll
+                for (int k = 0; k < 4; k++) Yv[2 + k] = pf[k];
+#pragma unroll
+                for (int k = 0; k < 4; k++) pf[k] = Yw[(t0 + 4 + k) * 64 + L];   // steps t0+5.. (padded)
+                bool have_u = false;
+                uint4 u4 = make_uint4(0u, 0u, 0u, 0u);
+                const int nb = m - t0 + 1 < 4 ? m - t0 + 1 : 4;
+                // Speculative pass: every step of the block evaluated against the
+                // state at the block start (four independent chains of work).  If
+                // no site of the block accepts, the block is finished here exactly
+                // as the sequential sweep would finish it (the state never changed);
+                // otherwise it is swept sequentially from its first step.
+                bool done = false;
+                if (spec) {
+                    int dE0 = 0, dE1 = 0, dE2 = 0, dE3 = 0;
+                    uint64_t lt0 = 0, lt1 = 0, lt2 = 0, lt3 = 0;
+#define UAVQ_SPEC_ROW(i, dEi, lti)                                                            \
+    if (t0 + i <= m) {                                                                       \
+        const int xb = (int)((cm >> (t0 + i - 1)) & 1ull);                                   \
+        const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) +                         \
+                      twoP * (int)__popcll(ballot64(xb != 0));                               \
+        dEi = xb ? -h : h;                                                                   \
+        lti = ballot64(dEi < dcut) & lanes_m;                                                \
+    }
+                    UAVQ_SPEC_ROW(0, dE0, lt0)
+                    UAVQ_SPEC_ROW(1, dE1, lt1)
+                    UAVQ_SPEC_ROW(2, dE2, lt2)
+                    UAVQ_SPEC_ROW(3, dE3, lt3)
+#undef UAVQ_SPEC_ROW
+                    const uint64_t any = lt0 | lt1 | lt2 | lt3;
+                    if (!any) {
+                        done = true;                 // nothing below the cut: all rejected, no draw
+                    } else {
+                        const uint64_t le = (ballot64(dE0 <= 0) & lt0) | (ballot64(dE1 <= 0) & lt1) |
+                                            (ballot64(dE2 <= 0) & lt2) | (ballot64(dE3 <= 0) & lt3);
+                        if (!le) {
+                            // only draws: take them all; the block is finished if none accepts
+                            uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
                             asm volatile("" : "+v"(cbase));   // generator stays inside this branch
                             u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
-                            blk = tb;
+                            have_u = true;
+                            const bool n0 = (lt0 >> L) & 1ull, n1 = (lt1 >> L) & 1ull;
+                            const bool n2 = (lt2 >> L) & 1ull, n3 = (lt3 >> L) & 1ull;
+                            const uint32_t th0 = n0 ? thr[dE0] : 0u, th1 = n1 ? thr[dE1] : 0u;
+                            const uint32_t th2 = n2 ? thr[dE2] : 0u, th3 = n3 ? thr[dE3] : 0u;
+                            const bool acc = (n0 && u4.x < th0) || (n1 && u4.y < th1) || (n2 && u4.z < th2) ||
+                                             (n3 && u4.w < th3);
+                            if (!ballot64(acc)) {
+                                done = true;
+                                ndraw_s += (uint32_t)(__popcll(lt0) + __popcll(lt1) + __popcll(lt2) + __popcll(lt3));
+                            }
                         }
-                        uint32_t thv = 0u;
-                        if (need) thv = thr[dE];
-                        accm |= ballot64(need && pick4(u4, (t - 1) & 3) < thv);
                     }
-                    if (!accm) {
-                        ndraw += __popcll(needm);
-                        break;
-                    }
-                    const int cstar = __builtin_ctzll(accm);
-                    const uint64_t upto = cstar == 63 ? ~0ull : ((2ull << cstar) - 1ull);
-                    ndraw += __popcll(needm & upto);
-                    E += (int64_t)__builtin_amdgcn_readlane(dE, cstar);
-                    nacc++;
-                    const int sign = ((rmask >> cstar) & 1ull) ? -1 : 1;
-                    rmask ^= 1ull << cstar;
-                    R += sign;
-                    if (L == cstar) {
-                        cm ^= 1ull << (t - 1);
-                        Cc += sign;
-                    }
-                    if (lane_in) Yc += sign * (int)sD[cstar * m + L];
-                    changed = true;
-                    open &= ~upto;
-                    if (!open) break;
                 }
-                if (changed) Yw[(t - 1) * 64 + L] = (uint16_t)Yc;
-                Yp = Yc;
-                Yc = Yn;
-                Yn = Ynn;
+                const int first = done ? 4 : 0;
+                const uint32_t acc_before = nacc_s;
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int t = t0 + i;
+                    if (t > m) break;
+                    if (i < first) continue;
+                    const int xb = (int)((cm >> (t - 1)) & 1ull);
+                    uint64_t rmask = ballot64(xb != 0);
+                    // 2P R_t, wave-uniform, updated by +-2P per accepted flip
+                    int hR = __builtin_amdgcn_readfirstlane(twoP * (int)__popcll(rmask));
+                    const int base = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0);
+                    uint64_t openm = lanes_m;
+                    int dErow = 0, dY = 0;
+                    bool changed = false;
+                    while (true) {
+                        const int h = base + hR;
+                        const int dE = xb ? -h : h;
+                        const uint64_t le0m = ballot64(dE <= 0);
+                        const uint64_t ltm = ballot64(dE < dcut);
+                        uint64_t accm = le0m & openm;
+                        const uint64_t needm = ltm & ~le0m & openm;
+                        if (needm) {
+                            if (!have_u) {
+                                uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
+                                asm volatile("" : "+v"(cbase));   // generator stays inside this branch
+                                u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
+                                have_u = true;
+                            }
+                            const bool need = (needm >> L) & 1ull;
+                            uint32_t thv = 0u;
+                            if (need) thv = thr[dE];
+                            const uint32_t u = i == 0 ? u4.x : (i == 1 ? u4.y : (i == 2 ? u4.z : u4.w));
+                            accm |= ballot64(need && u < thv);
+                        }
+                        if (!accm) {
+                            ndraw_s += (uint32_t)__popcll(needm);
+                            break;
+                        }
+                        const int cstar = __builtin_ctzll(accm);
+                        const uint64_t upto = cstar == 63 ? ~0ull : ((2ull << cstar) - 1ull);
+                        ndraw_s += (uint32_t)__popcll(needm & upto);
+                        dErow += __builtin_amdgcn_readlane(dE, cstar);
+                        nacc_s++;
+                        const bool add = !((rmask >> cstar) & 1ull);   // the flip sets x_{t,c*}
+                        rmask ^= 1ull << cstar;
+                        hR += add ? twoP : -twoP;
+                        if (L == cstar) {
+                            cm ^= 1ull << (t - 1);
+                            Kc += add ? twoP : -twoP;
+                        }
+                        const int dv = lane_in ? (int)sD[cstar * m + L] : 0;
+                        dY += add ? dv : -dv;
+                        changed = true;
+                        openm &= ~upto;
+                        if (!openm) break;
+                    }
+                    if (changed) {
+                        Yv[i + 1] += dY;
+                        E += dErow;
+                        Yw[(t - 1) * 64 + L] = (uint16_t)Yv[i + 1];
+                    }
+                }
+                Yv0 = Yv[4];
+                Yv1 = Yv[5];
+                // speculate on the next block only after a block without accepted flips
+                spec = nacc_s == acc_before;
             }
+            nacc += nacc_s;
+            ndraw += ndraw_s;
             if (E < bestE) {
                 bestE = E;
                 bestS = s;
@@ -751,7 +833,8 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a) {
 
 // ------------------------------------------------------------- launchers --
 static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
-    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + (size_t)wpb * 64 * m * 2;
+    // per replica: travel rows of steps 1..m plus 8 boundary rows, 64 int16 each
+    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + (size_t)wpb * 64 * (m + 8) * 2;
 }
 
 static size_t factored_lds_bytes(const uavq_plan *pl, int m) {
