@@ -350,7 +350,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     std::vector<uint32_t> thr((size_t)S * (Dmax + 1));
     uavq_schedule(p->T0, p->T1, S, &Dmax, thr.data());
     // device copy with rows padded to a multiple of 4 entries (16-byte rows)
-    pl->thr_stride = (Dmax + 1 + 3) & ~3;
+    pl->thr_stride = (Dmax + 2 + 3) & ~3;   // entries 0..Dmax, then zeros (at least one)
     std::vector<uint32_t> thr_dev((size_t)S * pl->thr_stride, 0u);
     for (int32_t s = 0; s < S; s++)
         std::memcpy(&thr_dev[(size_t)s * pl->thr_stride], &thr[(size_t)s * (Dmax + 1)], 4 * (size_t)(Dmax + 1));

@@ -51,6 +51,7 @@ struct KArgs {
     int32_t thr_stride;         // multiple of 4
     const int32_t *dcut;        // S: least d with thr[s][d] == 0
     int32_t S, Dmax;
+    float tl2_a, tl2_b;         // T_s ln 2 ~= exp2(tl2_a + tl2_b s): starting guess for acceptance cuts
     uint32_t seed;
     int32_t n_inst;
     int64_t total_rep;

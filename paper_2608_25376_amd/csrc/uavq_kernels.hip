@@ -28,6 +28,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
@@ -256,6 +257,8 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         }
         const uint32_t *thr = sthr + (s & 1) * Ts;
         const int dcut = uniform_load(a.dcut, s);
+        const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
+        const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
         if (active && s >= s0) {
             // Yp = Y_{t-1} (final), Yc = Y_t (updated on flips), Yn = Y_{t+1}, Ynn = Y_{t+2}
             int Yp[NJ], Yc[NJ], Yn[NJ], Ynn[NJ];
@@ -468,6 +471,27 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
 }
 
 
+// Acceptance cut of one site: the least d >= 1 whose table entry thr(d) is
+// <= u, so that a flip with energy change dE is accepted exactly when dE < cut
+// (dE <= 0 always; 0 < dE < dcut iff u < thr(dE); thr(d) = 0 from dcut on).
+// The continuous threshold 2^32 exp(-d/T) drops to u at d = T ln 2 (32 -
+// log2 u); a guess half a step below that (e0 = 32 T ln 2 - 1/2) is the cut or
+// one short of it, which the entries d-1, d, d+1 settle.  Otherwise (never
+// seen: the guess is good to far better than half a step; or u = 2^32 - 1)
+// the table is walked.  The result depends on the table alone.  The LDS row
+// must hold valid entries up to index dcut + 1.
+__device__ __forceinline__ int accept_cut(uint32_t u, float tl2, float e0, float dm1, int dcut, const uint32_t *thr) {
+    const float e = fmaf(-tl2, __builtin_amdgcn_logf((float)u), e0);   // u = 0: +inf
+    const int d = (int)__builtin_amdgcn_fmed3f(e, 0.0f, dm1) + 1;      // 1..dcut
+    const uint32_t tm = thr[d - 1], t0 = thr[d], t1 = thr[d + 1];
+    int cut = t0 > u ? d + 1 : d;
+    if (!(tm > u && t1 <= u)) {
+        while (cut < dcut && thr[cut] > u) cut++;
+        while (cut > 1 && thr[cut - 1] <= u) cut--;
+    }
+    return cut;
+}
+
 // ------------------------------------------------ sweep, LDS-resident rows --
 // Variant for m <= 64 (one cell per lane): lane c keeps its cell's column of
 // the state as a 64-bit step mask, and the travel rows Y_t (t = 1..m) are
@@ -509,7 +533,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     __syncthreads();
     const int s_first = s_first_sh;
     if (s_first < a.S) {
-        const int n4 = (uniform_load(a.dcut, s_first) + 3) >> 2;
+        const int n4 = (uniform_load(a.dcut, s_first) + 2 + 3) >> 2;   // through index dcut + 1
         const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
         uint4 *dst = reinterpret_cast<uint4 *>(sthr + (s_first & 1) * Ts);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
@@ -569,12 +593,12 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     uint64_t bestcm = cm;
     int Kc = twoP * (Cc - 1);   // 2P (C_c - 1): the cell-count part of the field
     uint64_t nacc = 0, ndraw = 0;
-    const int closed_dep = d.closed ? dep : 0;
+    int Elane = 0;   // energy change of the lane's accepted flips in the current sweep
 
     for (int s = s_first; s < a.S; s++) {
         uint4 pre[KP];
         const bool has_next = s + 1 < a.S;
-        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 3) >> 2 : 0;
+        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 2 + 3) >> 2 : 0;
         const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
 #pragma unroll
         for (int k = 0; k < KP; k++) {
@@ -583,6 +607,8 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         }
         const uint32_t *thr = sthr + (s & 1) * Ts;
         const int dcut = uniform_load(a.dcut, s);
+        const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
+        const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
         if (active && s >= s0) {
             // Steps are visited in blocks of four (the Philox blocks); Yv[k] holds
             // Y_{t0-1+k} for the block starting at step t0, and the travel rows of
@@ -654,64 +680,89 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 }
                 const int first = done ? 4 : 0;
                 const uint32_t acc_before = nacc_s;
+                // Sequential walk.  Until a site of the block needs a draw the
+                // cut is 1 (accept iff dE <= 0); from then on the exact cuts of
+                // the block's four steps make every acceptance test one compare.
+                bool have_cut = false;
+                int cut0 = 1, cut1 = 1, cut2 = 1, cut3 = 1;
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
                     const int t = t0 + i;
                     if (t > m) break;
                     if (i < first) continue;
-                    const int xb = (int)((cm >> (t - 1)) & 1ull);
-                    uint64_t rmask = ballot64(xb != 0);
-                    // 2P R_t, wave-uniform, updated by +-2P per accepted flip
-                    int hR = __builtin_amdgcn_readfirstlane(twoP * (int)__popcll(rmask));
-                    const int base = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0);
-                    uint64_t openm = lanes_m;
-                    int dErow = 0, dY = 0;
-                    bool changed = false;
-                    while (true) {
-                        const int h = base + hR;
-                        const int dE = xb ? -h : h;
-                        const uint64_t le0m = ballot64(dE <= 0);
-                        const uint64_t ltm = ballot64(dE < dcut);
-                        uint64_t accm = le0m & openm;
-                        const uint64_t needm = ltm & ~le0m & openm;
-                        if (needm) {
-                            if (!have_u) {
-                                uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
-                                asm volatile("" : "+v"(cbase));   // generator stays inside this branch
-                                u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
-                                have_u = true;
-                            }
-                            const bool need = (needm >> L) & 1ull;
-                            uint32_t thv = 0u;
-                            if (need) thv = thr[dE];
-                            const uint32_t u = i == 0 ? u4.x : (i == 1 ? u4.y : (i == 2 ? u4.z : u4.w));
-                            accm |= ballot64(need && u < thv);
-                        }
-                        if (!accm) {
-                            ndraw_s += (uint32_t)__popcll(needm);
-                            break;
-                        }
+                    const bool xb = (cm >> (t - 1)) & 1ull;
+                    const uint64_t rmask = ballot64(xb);
+                    const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) + twoP * (int)__popcll(rmask);
+                    const int dE0 = xb ? -h : h;            // dE against the state at the step start
+                    const int dplus = xb ? -twoP : twoP;    // change of dE per net 1 gained by step t
+                    uint64_t openm = lanes_m, accd = 0;
+                    int k = 0;                              // net 1s gained by step t so far
+                    int dY = 0, pdv = 0, psg = 0;           // cost-row entry of the last flip, added one step late
+                    // flip the first accepted site of accm
+                    auto flip = [&](uint64_t accm) {
                         const int cstar = __builtin_ctzll(accm);
-                        const uint64_t upto = cstar == 63 ? ~0ull : ((2ull << cstar) - 1ull);
-                        ndraw_s += (uint32_t)__popcll(needm & upto);
-                        dErow += __builtin_amdgcn_readlane(dE, cstar);
-                        nacc_s++;
-                        const bool add = !((rmask >> cstar) & 1ull);   // the flip sets x_{t,c*}
-                        rmask ^= 1ull << cstar;
-                        hR += add ? twoP : -twoP;
-                        if (L == cstar) {
-                            cm ^= 1ull << (t - 1);
-                            Kc += add ? twoP : -twoP;
+                        accd |= 1ull << cstar;
+                        dY += __mul24(psg, pdv);
+                        // lanes >= m read bytes past the row; their travel entries are never used
+                        pdv = sD[cstar * m + L];
+                        psg = ((rmask >> cstar) & 1ull) ? -1 : 1;   // +1: the flip sets x_{t,c*}
+                        k += psg;
+                        openm &= ~1ull << cstar;
+                    };
+                    bool walking = true;
+                    if (!have_cut) {
+                        // no exact cut yet: accept iff dE <= 0 while no open site needs a draw
+                        while (true) {
+                            const int dE = dE0 + __mul24(k, dplus);
+                            if (ballot64((uint32_t)(dE - 1) < (uint32_t)(dcut - 1)) & openm) {
+                                have_cut = true;
+                                if (!have_u) {
+                                    uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
+                                    asm volatile("" : "+v"(cbase));   // generator stays inside this branch
+                                    u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
+                                    have_u = true;
+                                }
+                                cut0 = accept_cut(u4.x, tl2, e0, dm1, dcut, thr);
+                                cut1 = accept_cut(u4.y, tl2, e0, dm1, dcut, thr);
+                                cut2 = accept_cut(u4.z, tl2, e0, dm1, dcut, thr);
+                                cut3 = accept_cut(u4.w, tl2, e0, dm1, dcut, thr);
+                                break;
+                            }
+                            const uint64_t accm = ballot64(dE <= 0) & openm;
+                            if (!accm) {
+                                walking = false;
+                                break;
+                            }
+                            flip(accm);
                         }
-                        const int dv = lane_in ? (int)sD[cstar * m + L] : 0;
-                        dY += add ? dv : -dv;
-                        changed = true;
-                        openm &= ~upto;
-                        if (!openm) break;
                     }
-                    if (changed) {
+                    if (walking) {
+                        const int cut = i == 0 ? cut0 : (i == 1 ? cut1 : (i == 2 ? cut2 : cut3));
+                        const int rel = cut - dE0;          // accept iff k dplus < cut - dE0
+                        uint64_t accm = ballot64(__mul24(k, dplus) < rel) & openm;
+                        while (accm) {
+                            flip(accm);
+                            accm = ballot64(__mul24(k, dplus) < rel) & openm;
+                        }
+                    }
+                    dY += __mul24(psg, pdv);
+                    // the dE each site was visited with: dE0 plus dplus per net flip before it
+                    int dEv = dE0;
+                    if (accd) {
+                        const uint64_t adds = accd & ~rmask, rems = accd & rmask;
+                        const int na = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(adds >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)adds, 0u));
+                        const int nr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(rems >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rems, 0u));
+                        dEv = dE0 + __mul24(na - nr, dplus);
+                    }
+                    ndraw_s += (uint32_t)__popcll(ballot64((uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)) & lanes_m);
+                    if (accd) {
+                        nacc_s += (uint32_t)__popcll(accd);
+                        if ((accd >> L) & 1ull) {
+                            cm ^= 1ull << (t - 1);
+                            Kc += dplus;
+                            Elane += dEv;
+                        }
                         Yv[i + 1] += dY;
-                        E += dErow;
                         Yw[(t - 1) * 64 + L] = (uint16_t)Yv[i + 1];
                     }
                 }
@@ -722,6 +773,10 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             }
             nacc += nacc_s;
             ndraw += ndraw_s;
+            if (nacc_s) {
+                E += wave_sum64((int64_t)Elane);
+                Elane = 0;
+            }
             if (E < bestE) {
                 bestE = E;
                 bestS = s;
@@ -1020,6 +1075,8 @@ int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const ua
     a.S = pl->S;
     a.Dmax = pl->Dmax;
     a.thr_stride = pl->thr_stride;
+    a.tl2_a = (float)std::log2((double)pl->p.T0 * 0.69314718055994531);
+    a.tl2_b = pl->S > 1 ? (float)(std::log2((double)pl->p.T1 / (double)pl->p.T0) / (pl->S - 1)) : 0.0f;
     a.seed = pl->p.seed;
     a.n_inst = pl->n_inst;
     a.total_rep = pl->total_rep;
