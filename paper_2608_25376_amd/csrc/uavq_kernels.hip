@@ -637,133 +637,122 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 // as the sequential sweep would finish it (the state never changed);
                 // otherwise it is swept sequentially from its first step.
                 bool done = false;
-                if (spec) {
-                    int dE0 = 0, dE1 = 0, dE2 = 0, dE3 = 0;
-                    uint64_t lt0 = 0, lt1 = 0, lt2 = 0, lt3 = 0;
-#define UAVQ_SPEC_ROW(i, dEi, lti)                                                            \
-    if (t0 + i <= m) {                                                                       \
-        const int xb = (int)((cm >> (t0 + i - 1)) & 1ull);                                   \
-        const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) +                         \
-                      twoP * (int)__popcll(ballot64(xb != 0));                               \
-        dEi = xb ? -h : h;                                                                   \
-        lti = ballot64(dEi < dcut) & lanes_m;                                                \
-    }
-                    UAVQ_SPEC_ROW(0, dE0, lt0)
-                    UAVQ_SPEC_ROW(1, dE1, lt1)
-                    UAVQ_SPEC_ROW(2, dE2, lt2)
-                    UAVQ_SPEC_ROW(3, dE3, lt3)
-#undef UAVQ_SPEC_ROW
-                    const uint64_t any = lt0 | lt1 | lt2 | lt3;
-                    if (!any) {
+                if (spec && t0 + 3 <= m) {
+                    // four independent evaluations, no branches between them
+                    int dEs[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        const bool xb = (cm >> (t0 + i - 1)) & 1ull;
+                        const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) + twoP * (int)__popcll(ballot64(xb));
+                        dEs[i] = xb ? -h : h;
+                    }
+                    const int mn = min(min(dEs[0], dEs[1]), min(dEs[2], dEs[3]));
+                    if (!(ballot64(mn < dcut) & lanes_m)) {
                         done = true;                 // nothing below the cut: all rejected, no draw
-                    } else {
-                        const uint64_t le = (ballot64(dE0 <= 0) & lt0) | (ballot64(dE1 <= 0) & lt1) |
-                                            (ballot64(dE2 <= 0) & lt2) | (ballot64(dE3 <= 0) & lt3);
-                        if (!le) {
-                            // only draws: take them all; the block is finished if none accepts
-                            uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
-                            asm volatile("" : "+v"(cbase));   // generator stays inside this branch
-                            u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
-                            have_u = true;
-                            const bool n0 = (lt0 >> L) & 1ull, n1 = (lt1 >> L) & 1ull;
-                            const bool n2 = (lt2 >> L) & 1ull, n3 = (lt3 >> L) & 1ull;
-                            const uint32_t th0 = n0 ? thr[dE0] : 0u, th1 = n1 ? thr[dE1] : 0u;
-                            const uint32_t th2 = n2 ? thr[dE2] : 0u, th3 = n3 ? thr[dE3] : 0u;
-                            const bool acc = (n0 && u4.x < th0) || (n1 && u4.y < th1) || (n2 && u4.z < th2) ||
-                                             (n3 && u4.w < th3);
-                            if (!ballot64(acc)) {
-                                done = true;
-                                ndraw_s += (uint32_t)(__popcll(lt0) + __popcll(lt1) + __popcll(lt2) + __popcll(lt3));
-                            }
+                    } else if (!(ballot64(mn <= 0) & lanes_m)) {
+                        // only draws: take them all; the block is finished if none accepts
+                        uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
+                        asm volatile("" : "+v"(cbase));   // generator stays inside this branch
+                        u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
+                        have_u = true;
+                        const bool n0 = lane_in && dEs[0] < dcut, n1 = lane_in && dEs[1] < dcut;
+                        const bool n2 = lane_in && dEs[2] < dcut, n3 = lane_in && dEs[3] < dcut;
+                        const uint32_t th0 = n0 ? thr[dEs[0]] : 0u, th1 = n1 ? thr[dEs[1]] : 0u;
+                        const uint32_t th2 = n2 ? thr[dEs[2]] : 0u, th3 = n3 ? thr[dEs[3]] : 0u;
+                        const bool acc = u4.x < th0 || u4.y < th1 || u4.z < th2 || u4.w < th3;
+                        if (!ballot64(acc)) {
+                            done = true;
+                            ndraw_s += (uint32_t)(__popcll(ballot64(n0)) + __popcll(ballot64(n1)) +
+                                                  __popcll(ballot64(n2)) + __popcll(ballot64(n3)));
                         }
                     }
                 }
-                const int first = done ? 4 : 0;
                 const uint32_t acc_before = nacc_s;
-                // Sequential walk.  Until a site of the block needs a draw the
-                // cut is 1 (accept iff dE <= 0); from then on the exact cuts of
-                // the block's four steps make every acceptance test one compare.
-                bool have_cut = false;
-                int cut0 = 1, cut1 = 1, cut2 = 1, cut3 = 1;
+                if (!done) {
+                    // Sequential walk.  Until a site of the block needs a draw the
+                    // cut is 1 (accept iff dE <= 0); from then on the exact cuts of
+                    // the block's four steps make every acceptance test one compare.
+                    bool have_cut = false;
+                    int cut0 = 1, cut1 = 1, cut2 = 1, cut3 = 1;
 #pragma unroll
-                for (int i = 0; i < 4; i++) {
-                    const int t = t0 + i;
-                    if (t > m) break;
-                    if (i < first) continue;
-                    const bool xb = (cm >> (t - 1)) & 1ull;
-                    const uint64_t rmask = ballot64(xb);
-                    const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) + twoP * (int)__popcll(rmask);
-                    const int dE0 = xb ? -h : h;            // dE against the state at the step start
-                    const int dplus = xb ? -twoP : twoP;    // change of dE per net 1 gained by step t
-                    uint64_t openm = lanes_m, accd = 0;
-                    int k = 0;                              // net 1s gained by step t so far
-                    int dY = 0, pdv = 0, psg = 0;           // cost-row entry of the last flip, added one step late
-                    // flip the first accepted site of accm
-                    auto flip = [&](uint64_t accm) {
-                        const int cstar = __builtin_ctzll(accm);
-                        accd |= 1ull << cstar;
-                        dY += __mul24(psg, pdv);
-                        // lanes >= m read bytes past the row; their travel entries are never used
-                        pdv = sD[cstar * m + L];
-                        psg = ((rmask >> cstar) & 1ull) ? -1 : 1;   // +1: the flip sets x_{t,c*}
-                        k += psg;
-                        openm &= ~1ull << cstar;
-                    };
-                    bool walking = true;
-                    if (!have_cut) {
-                        // no exact cut yet: accept iff dE <= 0 while no open site needs a draw
-                        while (true) {
-                            const int dE = dE0 + __mul24(k, dplus);
-                            if (ballot64((uint32_t)(dE - 1) < (uint32_t)(dcut - 1)) & openm) {
-                                have_cut = true;
-                                if (!have_u) {
-                                    uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
-                                    asm volatile("" : "+v"(cbase));   // generator stays inside this branch
-                                    u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
-                                    have_u = true;
+                    for (int i = 0; i < 4; i++) {
+                        const int t = t0 + i;
+                        if (t > m) break;
+                        const bool xb = (cm >> (t - 1)) & 1ull;
+                        const uint64_t rmask = ballot64(xb);
+                        const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) + twoP * (int)__popcll(rmask);
+                        const int dE0 = xb ? -h : h;            // dE against the state at the step start
+                        const int dplus = xb ? -twoP : twoP;    // change of dE per net 1 gained by step t
+                        uint64_t openm = lanes_m, accd = 0;
+                        int k = 0;                              // net 1s gained by step t so far
+                        int dY = 0, pdv = 0, psg = 0;           // cost-row entry of the last flip, added one step late
+                        // flip the first accepted site of accm
+                        auto flip = [&](uint64_t accm) {
+                            const int cstar = __builtin_ctzll(accm);
+                            accd |= 1ull << cstar;
+                            dY += __mul24(psg, pdv);
+                            // lanes >= m read bytes past the row; their travel entries are never used
+                            pdv = sD[cstar * m + L];
+                            psg = ((rmask >> cstar) & 1ull) ? -1 : 1;   // +1: the flip sets x_{t,c*}
+                            k += psg;
+                            openm &= ~1ull << cstar;
+                        };
+                        bool walking = true;
+                        if (!have_cut) {
+                            // no exact cut yet: accept iff dE <= 0 while no open site needs a draw
+                            while (true) {
+                                const int dE = dE0 + __mul24(k, dplus);
+                                if (ballot64((uint32_t)(dE - 1) < (uint32_t)(dcut - 1)) & openm) {
+                                    have_cut = true;
+                                    if (!have_u) {
+                                        uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
+                                        asm volatile("" : "+v"(cbase));   // generator stays inside this branch
+                                        u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
+                                        have_u = true;
+                                    }
+                                    cut0 = accept_cut(u4.x, tl2, e0, dm1, dcut, thr);
+                                    cut1 = accept_cut(u4.y, tl2, e0, dm1, dcut, thr);
+                                    cut2 = accept_cut(u4.z, tl2, e0, dm1, dcut, thr);
+                                    cut3 = accept_cut(u4.w, tl2, e0, dm1, dcut, thr);
+                                    break;
                                 }
-                                cut0 = accept_cut(u4.x, tl2, e0, dm1, dcut, thr);
-                                cut1 = accept_cut(u4.y, tl2, e0, dm1, dcut, thr);
-                                cut2 = accept_cut(u4.z, tl2, e0, dm1, dcut, thr);
-                                cut3 = accept_cut(u4.w, tl2, e0, dm1, dcut, thr);
-                                break;
+                                const uint64_t accm = ballot64(dE <= 0) & openm;
+                                if (!accm) {
+                                    walking = false;
+                                    break;
+                                }
+                                flip(accm);
                             }
-                            const uint64_t accm = ballot64(dE <= 0) & openm;
-                            if (!accm) {
-                                walking = false;
-                                break;
+                        }
+                        if (walking) {
+                            const int cut = i == 0 ? cut0 : (i == 1 ? cut1 : (i == 2 ? cut2 : cut3));
+                            const int rel = cut - dE0;          // accept iff k dplus < cut - dE0
+                            uint64_t accm = ballot64(__mul24(k, dplus) < rel) & openm;
+                            while (accm) {
+                                flip(accm);
+                                accm = ballot64(__mul24(k, dplus) < rel) & openm;
                             }
-                            flip(accm);
                         }
-                    }
-                    if (walking) {
-                        const int cut = i == 0 ? cut0 : (i == 1 ? cut1 : (i == 2 ? cut2 : cut3));
-                        const int rel = cut - dE0;          // accept iff k dplus < cut - dE0
-                        uint64_t accm = ballot64(__mul24(k, dplus) < rel) & openm;
-                        while (accm) {
-                            flip(accm);
-                            accm = ballot64(__mul24(k, dplus) < rel) & openm;
+                        dY += __mul24(psg, pdv);
+                        // the dE each site was visited with: dE0 plus dplus per net flip before it
+                        int dEv = dE0;
+                        if (accd) {
+                            const uint64_t adds = accd & ~rmask, rems = accd & rmask;
+                            const int na = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(adds >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)adds, 0u));
+                            const int nr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(rems >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rems, 0u));
+                            dEv = dE0 + __mul24(na - nr, dplus);
                         }
-                    }
-                    dY += __mul24(psg, pdv);
-                    // the dE each site was visited with: dE0 plus dplus per net flip before it
-                    int dEv = dE0;
-                    if (accd) {
-                        const uint64_t adds = accd & ~rmask, rems = accd & rmask;
-                        const int na = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(adds >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)adds, 0u));
-                        const int nr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(rems >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rems, 0u));
-                        dEv = dE0 + __mul24(na - nr, dplus);
-                    }
-                    ndraw_s += (uint32_t)__popcll(ballot64((uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)) & lanes_m);
-                    if (accd) {
-                        nacc_s += (uint32_t)__popcll(accd);
-                        if ((accd >> L) & 1ull) {
-                            cm ^= 1ull << (t - 1);
-                            Kc += dplus;
-                            Elane += dEv;
+                        ndraw_s += (uint32_t)__popcll(ballot64((uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)) & lanes_m);
+                        if (accd) {
+                            nacc_s += (uint32_t)__popcll(accd);
+                            if ((accd >> L) & 1ull) {
+                                cm ^= 1ull << (t - 1);
+                                Kc += dplus;
+                                Elane += dEv;
+                            }
+                            Yv[i + 1] += dY;
+                            Yw[(t - 1) * 64 + L] = (uint16_t)Yv[i + 1];
                         }
-                        Yv[i + 1] += dY;
-                        Yw[(t - 1) * 64 + L] = (uint16_t)Yv[i + 1];
                     }
                 }
                 Yv0 = Yv[4];
