@@ -638,13 +638,23 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 // otherwise it is swept sequentially from its first step.
                 bool done = false;
                 if (spec && t0 + 3 <= m) {
-                    // four independent evaluations, no branches between them
-                    int dEs[4];
+                    // four independent evaluations, staged side by side with no
+                    // branches between them: dE = A + 2P R_t for x = 0 and
+                    // 4P - 2P R_t - A for x = 1, A = Y_{t-1} + Y_{t+1} + 2P (C_c - 1)
+                    const uint32_t xbits = (uint32_t)(cm >> (t0 - 1));
+                    bool xb[4];
+                    uint64_t rm[4];
+                    int A[4], dEs[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) xb[i] = (xbits >> i) & 1u;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) rm[i] = ballot64(xb[i]);
+#pragma unroll
+                    for (int i = 0; i < 4; i++) A[i] = Yv[i] + Yv[i + 2] + Kc;
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
-                        const bool xb = (cm >> (t0 + i - 1)) & 1ull;
-                        const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) + twoP * (int)__popcll(ballot64(xb));
-                        dEs[i] = xb ? -h : h;
+                        const int c1 = __builtin_amdgcn_readfirstlane(twoP * (int)__popcll(rm[i]));
+                        dEs[i] = xb[i] ? (2 * twoP - c1) - A[i] : A[i] + c1;
                     }
                     const int mn = min(min(dEs[0], dEs[1]), min(dEs[2], dEs[3]));
                     if (!(ballot64(mn < dcut) & lanes_m)) {
@@ -825,6 +835,18 @@ __global__ __launch_bounds__(1024) void k_sweep_ylds(KArgs a) {
     }
 }
 
+// Same sweep for launches that hold at most one wave per SIMD: each replica's
+// walk is a latency-bound chain, so with no other wave to switch to the
+// compiler may spend registers on overlapping independent work instead.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_sweep_ylds_w1(KArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int iter = 0;; iter++) {
+        const int itx = next_item(a, iter);
+        if (itx < 0) break;
+        ylds_item(a, itx, smem);
+    }
+}
+
 __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -899,7 +921,8 @@ bool ylds_fits(const uavq_plan *pl) {
 static bool use_ylds(const uavq_plan *pl) { return pl->variant != UAVQ_VARIANT_ROWMASK && ylds_fits(pl); }
 
 static const void *class_kernel(const uavq_plan *pl, int cls) {
-    if (cls == 1) return use_ylds(pl) ? (const void *)k_sweep_ylds : (const void *)k_sweep_factored<1>;
+    if (cls == 1 && use_ylds(pl)) return pl->ylds_w1 ? (const void *)k_sweep_ylds_w1 : (const void *)k_sweep_ylds;
+    if (cls == 1) return (const void *)k_sweep_factored<1>;
     if (cls == 2) return (const void *)k_sweep_factored<2>;
     return (const void *)k_sweep_factored<3>;
 }
@@ -912,6 +935,11 @@ static int prepare(const uavq_plan *cpl) {
     int dev = 0;
     UAVQ_HIP(hipGetDevice(&dev));
     UAVQ_HIP(hipDeviceGetAttribute(&pl->cu_count, hipDeviceAttributeMultiprocessorCount, dev));
+    {
+        // one wave per SIMD when every wave of the m <= 64 launch is resident at once
+        const int n1 = pl->class_begin[2] - pl->class_begin[1], w1 = pl->waves_per_block[1];
+        pl->ylds_w1 = use_ylds(pl) && w1 <= 4 && (int64_t)n1 * w1 <= 4 * (int64_t)pl->cu_count;
+    }
     for (int cls = 1; cls <= kMaxChunks; cls++) {
         if (pl->dense || pl->class_begin[cls + 1] <= pl->class_begin[cls]) continue;
         const int mmax = class_mmax(pl, cls), wpb = pl->waves_per_block[cls];
@@ -946,7 +974,9 @@ static int launch_class(const uavq_plan *pl, KArgs a, int cls, hipStream_t st) {
     const bool timed = pl->timing && !pl->graph;
     if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls], st));
     const size_t lds = pl->lds_class[cls];
-    if (cls == 1 && use_ylds(pl))
+    if (cls == 1 && use_ylds(pl) && pl->ylds_w1)
+        hipLaunchKernelGGL(k_sweep_ylds_w1, dim3(grid), dim3(64 * wpb), lds, st, a);
+    else if (cls == 1 && use_ylds(pl))
         hipLaunchKernelGGL(k_sweep_ylds, dim3(grid), dim3(64 * wpb), lds, st, a);
     else if (cls == 1)
         hipLaunchKernelGGL(k_sweep_factored<1>, dim3(grid), dim3(64 * wpb), lds, st, a);
