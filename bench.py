@@ -8,8 +8,10 @@ Default workload: 8x8 field with Bernoulli(0.1) no-fly cells (54 free cells,
 2916 variables), 1024 replicas, 2000 sweeps, geometric T 200 -> 0.5, seed 1.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -42,7 +44,50 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="choose the launch shape with uavq_autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=0, help="oracle sample size (0 = auto)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES of device memory once (reference run for the HBM byte counters)")
     return ap.parse_args()
+
+
+# Sources of the sweep kernels; an HBM-traffic record applies only to the
+# build whose sources hash to the value stored with it.
+KERNEL_SOURCES = ["paper_2608_25376_amd/csrc/uavq_kernels.hip", "paper_2608_25376_amd/csrc/uavq_device.h",
+                  "paper_2608_25376_amd/csrc/uavq_internal.h"]
+
+
+def kernel_source_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    and workload (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or
+    None if there is none or the kernel sources changed since it was taken."""
+    name = re.sub(r"[^A-Za-z0-9_.]+", "_", f"{kernel}_{workload}_traffic").strip("_") + ".md"
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    sha = re.search(r"^source_sha256:\s*([0-9a-f]{64})\s*$", txt, re.M)
+    val = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)\s*$", txt, re.M)
+    if not sha or not val or sha.group(1) != kernel_source_sha256():
+        return None
+    return float(val.group(1))
+
+
+def copy_calibration(nbytes):
+    """One device-to-device copy of nbytes (the reference for the byte counters)."""
+    import torch
+    x = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes}), flush=True)
 
 
 def cpu_baseline(w, q_gpu_m, args):
@@ -81,6 +126,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration > 0:
+        copy_calibration(args.copy_calibration)
+        return
     w = inputs.workload(args.workload)
     dense = args.kernel == "dense"
     qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly, dense=dense) for g in w.grids]
@@ -129,6 +177,8 @@ def main():
     sweep_avg = float(np.mean(sweep_ms)) if sweep_ms else ms_per_step
     achieved = ops / (sweep_avg * 1e-3)
     value = attempts / (ms_per_step * 1e-3)
+    kernels = [k for k in (plan.kernel_name(c) for c in (1, 2, 3)) if k]
+    kernel = "+".join(kernels)
 
     res = {
         "metric": "spin-flip attempts/s",
@@ -150,9 +200,9 @@ def main():
                    "accept_rate": float(acc.sum() / attempts), "draw_rate": float(drw.sum() / attempts),
                    "best_E": [int(v) for v in out.inst_best_E.cpu().numpy()[:4]]},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_ALU_OPS / 1e12,
-                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / PEAK_ALU_OPS, "traffic": None,
-                     "kernel": "k_sweep_factored" if not dense else "k_sweep_dense",
-                     "kernel_ms": sweep_avg, "ops_per_launch": ops},
+                     "unit": "Tops/s (int32 lane-ops)", "frac": achieved / PEAK_ALU_OPS,
+                     "traffic": recorded_traffic(kernel, w.name),
+                     "kernel": kernel, "kernel_ms": sweep_avg, "ops_per_launch": ops},
     }
     if not args.no_cpu_baseline:
         res["cpu_baseline"] = cpu_baseline(w, qs[0].m, args)

@@ -177,6 +177,12 @@ typedef struct {
     int32_t Dmax;
 } uavq_plan_info_t;
 int uavq_plan_info(const uavq_plan *plan, uavq_plan_info_t *info);
+/* Name of the sweep kernel that uavq_anneal_batch launches for the
+ * instances of chunk class cls (1: m <= 64, 2: m <= 128, 3: m <= 192), for
+ * profiling and reports: "" if the class is empty, NULL on error (cls out of
+ * range, or no HIP device to decide the launch shape on).  The string is
+ * static. */
+const char *uavq_plan_kernel_name(const uavq_plan *plan, int32_t cls);
 /* Replica r of instance i is global replica rep_offset[i] + r; its packed
  * state starts at word state_offset[i] + r * state_words(i).  Arrays of
  * n_inst + 1 entries (host). */

@@ -257,8 +257,6 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         }
         const uint32_t *thr = sthr + (s & 1) * Ts;
         const int dcut = uniform_load(a.dcut, s);
-        const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
-        const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
         if (active && s >= s0) {
             // Yp = Y_{t-1} (final), Yc = Y_t (updated on flips), Yn = Y_{t+1}, Ynn = Y_{t+2}
             int Yp[NJ], Yc[NJ], Yn[NJ], Ynn[NJ];
@@ -630,7 +628,6 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 for (int k = 0; k < 4; k++) pf[k] = Yw[(t0 + 4 + k) * 64 + L];   // steps t0+5.. (padded)
                 bool have_u = false;
                 uint4 u4 = make_uint4(0u, 0u, 0u, 0u);
-                const int nb = m - t0 + 1 < 4 ? m - t0 + 1 : 4;
                 // Speculative pass: every step of the block evaluated against the
                 // state at the block start (four independent chains of work).  If
                 // no site of the block accepts, the block is finished here exactly
@@ -1068,6 +1065,18 @@ int uavq_plan_upload(const uavq_plan *pl, void *d_ws, size_t ws_bytes, void *str
     if (rc) return rc;
     UAVQ_HIP(hipMemcpyAsync(d_ws, pl->blob.data(), pl->blob.size(), hipMemcpyHostToDevice, (hipStream_t)stream));
     return UAVQ_OK;
+}
+
+const char *uavq_plan_kernel_name(const uavq_plan *pl, int32_t cls) {
+    if (!pl || cls < 1 || cls > uavq::kMaxChunks) {
+        set_error(UAVQ_EINVAL, "plan_kernel_name: bad argument");
+        return nullptr;
+    }
+    if (pl->dense) return pl->n_inst > 0 && cls == 1 ? "k_sweep_dense" : "";
+    if (pl->class_begin[cls + 1] <= pl->class_begin[cls]) return "";
+    if (uavq::prepare(pl)) return nullptr;   // the one-wave choice needs the device's CU count
+    if (cls == 1 && uavq::use_ylds(pl)) return pl->ylds_w1 ? "k_sweep_ylds_w1" : "k_sweep_ylds";
+    return cls == 1 ? "k_sweep_factored<1>" : (cls == 2 ? "k_sweep_factored<2>" : "k_sweep_factored<3>");
 }
 
 int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,

@@ -77,7 +77,8 @@ EXPORTS = [
     "uavq_last_error", "uavq_version", "uavq_qubo_build", "uavq_qubo_free", "uavq_qubo_info",
     "uavq_qubo_free_cells", "uavq_qubo_costs", "uavq_qubo_export", "uavq_energy_eval",
     "uavq_energy_workspace_bytes", "uavq_energy_eval_dev", "uavq_decode_path", "uavq_schedule",
-    "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_layout", "uavq_plan_upload",
+    "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_kernel_name", "uavq_plan_layout",
+    "uavq_plan_upload",
     "uavq_anneal_batch", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
     "uavq_mlp_param_count", "uavq_mlp_features", "uavq_mlp_workspace_bytes", "uavq_mlp_forward",
     "uavq_mlp_loss_grad", "uavq_mlp_adam", "uavq_quantize_marginals", "uavq_sample_seeds",
@@ -113,6 +114,8 @@ def lib():
         L.uavq_plan_free.argtypes = [vp]
         L.uavq_plan_free.restype = None
         L.uavq_plan_info.argtypes = [vp, P(_PlanInfo)]
+        L.uavq_plan_kernel_name.argtypes = [vp, C.c_int32]
+        L.uavq_plan_kernel_name.restype = C.c_char_p
         L.uavq_plan_layout.argtypes = [vp, P(C.c_int64), P(C.c_int64)]
         L.uavq_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
         L.uavq_anneal_batch.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), vp]
@@ -329,6 +332,13 @@ class Plan:
 
     def set_timing(self, enable=True):
         _check(lib().uavq_plan_set_timing(self._h, 1 if enable else 0))
+
+    def kernel_name(self, cls=1):
+        """Sweep kernel launched for chunk class cls (1: m <= 64, 2: <= 128, 3: <= 192); '' if unused."""
+        v = lib().uavq_plan_kernel_name(self._h, int(cls))
+        if v is None:
+            raise UavqError(-1, lib().uavq_last_error().decode())
+        return v.decode()
 
     def sweep_ms(self):
         """Elapsed ms of the sweep kernels of the last anneal (HIP events on its stream)."""

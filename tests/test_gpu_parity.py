@@ -164,3 +164,13 @@ def test_grid8x8_full_size_sampled(U, oracle_lib):
     w = inputs.workload("grid8x8_nofly0.1")
     g = w.grids[0]
     _check_instance(U, oracle_lib, g, w.replicas, w.sweeps, w.T0, w.T1, w.seed, reps=[0, 1, 2, 511, 777, 1023])
+
+
+def test_grid12x12_full_size_sampled(U, oracle_lib):
+    """The 12x12 configuration (143 free cells, 20449 variables, 4096
+    replicas, 4000 sweeps, T 200 -> 0.5; three cell chunks per lane) at full
+    size; the oracle recomputes three replicas one by one."""
+    w = inputs.workload("grid12x12")
+    g = w.grids[0]
+    assert g.n_free == 143 and w.replicas == 4096 and w.sweeps == 4000
+    _check_instance(U, oracle_lib, g, w.replicas, w.sweeps, w.T0, w.T1, w.seed, reps=[0, 2049, 4095])
