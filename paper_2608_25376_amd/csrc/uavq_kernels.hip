@@ -469,7 +469,7 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
 }
 
 
-// Acceptance cut of one site: the least d >= 1 whose table entry thr(d) is
+// Acceptance cuts of four sites: for each, the least d >= 1 whose table entry thr(d) is
 // <= u, so that a flip with energy change dE is accepted exactly when dE < cut
 // (dE <= 0 always; 0 < dE < dcut iff u < thr(dE); thr(d) = 0 from dcut on).
 // The continuous threshold 2^32 exp(-d/T) drops to u at d = T ln 2 (32 -
@@ -478,16 +478,42 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
 // seen: the guess is good to far better than half a step; or u = 2^32 - 1)
 // the table is walked.  The result depends on the table alone.  The LDS row
 // must hold valid entries up to index dcut + 1.
-__device__ __forceinline__ int accept_cut(uint32_t u, float tl2, float e0, float dm1, int dcut, const uint32_t *thr) {
-    const float e = fmaf(-tl2, __builtin_amdgcn_logf((float)u), e0);   // u = 0: +inf
-    const int d = (int)__builtin_amdgcn_fmed3f(e, 0.0f, dm1) + 1;      // 1..dcut
-    const uint32_t tm = thr[d - 1], t0 = thr[d], t1 = thr[d + 1];
-    int cut = t0 > u ? d + 1 : d;
-    if (!(tm > u && t1 <= u)) {
-        while (cut < dcut && thr[cut] > u) cut++;
-        while (cut > 1 && thr[cut - 1] <= u) cut--;
+__device__ __forceinline__ void accept_cuts(const uint4 &u4, float tl2, float e0, float dm1, int dcut,
+                                            const uint32_t *thr, int &cut0, int &cut1, int &cut2, int &cut3) {
+    const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
+    int d[4], cut[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const float e = fmaf(-tl2, __builtin_amdgcn_logf((float)u[i]), e0);   // u = 0: +inf
+        d[i] = (int)__builtin_amdgcn_fmed3f(e, 0.0f, dm1) + 1;                // 1..dcut
     }
-    return cut;
+    // all twelve entries are read unconditionally, so the reads issue together
+    uint32_t tm[4], t0[4], t1[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        tm[i] = thr[d[i] - 1];
+        t0[i] = thr[d[i]];
+        t1[i] = thr[d[i] + 1];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        cut[i] = d[i] + (t0[i] > u[i] ? 1 : 0);
+        ok = ok & (tm[i] > u[i]) & (t1[i] <= u[i]);
+    }
+    if (ballot64(!ok)) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            int c = cut[i];
+            while (c < dcut && thr[c] > u[i]) c++;
+            while (c > 1 && thr[c - 1] <= u[i]) c--;
+            cut[i] = c;
+        }
+    }
+    cut0 = cut[0];
+    cut1 = cut[1];
+    cut2 = cut[2];
+    cut3 = cut[3];
 }
 
 // ------------------------------------------------ sweep, LDS-resident rows --
@@ -591,7 +617,8 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     uint64_t bestcm = cm;
     int Kc = twoP * (Cc - 1);   // 2P (C_c - 1): the cell-count part of the field
     uint64_t nacc = 0, ndraw = 0;
-    int Elane = 0;   // energy change of the lane's accepted flips in the current sweep
+    int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
+    uint32_t ndraw_lane = 0;   // draws of the lane's sites visited by the sequential walk
 
     for (int s = s_first; s < a.S; s++) {
         uint4 pre[KP];
@@ -664,9 +691,11 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                         have_u = true;
                         const bool n0 = lane_in && dEs[0] < dcut, n1 = lane_in && dEs[1] < dcut;
                         const bool n2 = lane_in && dEs[2] < dcut, n3 = lane_in && dEs[3] < dcut;
-                        const uint32_t th0 = n0 ? thr[dEs[0]] : 0u, th1 = n1 ? thr[dEs[1]] : 0u;
-                        const uint32_t th2 = n2 ? thr[dEs[2]] : 0u, th3 = n3 ? thr[dEs[3]] : 0u;
-                        const bool acc = u4.x < th0 || u4.y < th1 || u4.z < th2 || u4.w < th3;
+                        // unconditional reads (index 0 where no draw happens) issue together
+                        const uint32_t r0 = thr[n0 ? dEs[0] : 0], r1 = thr[n1 ? dEs[1] : 0];
+                        const uint32_t r2 = thr[n2 ? dEs[2] : 0], r3 = thr[n3 ? dEs[3] : 0];
+                        const bool acc = (n0 & (u4.x < r0)) | (n1 & (u4.y < r1)) | (n2 & (u4.z < r2)) |
+                                         (n3 & (u4.w < r3));
                         if (!ballot64(acc)) {
                             done = true;
                             ndraw_s += (uint32_t)(__popcll(ballot64(n0)) + __popcll(ballot64(n1)) +
@@ -717,10 +746,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                                         u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id), a.seed, 0u);
                                         have_u = true;
                                     }
-                                    cut0 = accept_cut(u4.x, tl2, e0, dm1, dcut, thr);
-                                    cut1 = accept_cut(u4.y, tl2, e0, dm1, dcut, thr);
-                                    cut2 = accept_cut(u4.z, tl2, e0, dm1, dcut, thr);
-                                    cut3 = accept_cut(u4.w, tl2, e0, dm1, dcut, thr);
+                                    accept_cuts(u4, tl2, e0, dm1, dcut, thr, cut0, cut1, cut2, cut3);
                                     break;
                                 }
                                 const uint64_t accm = ballot64(dE <= 0) & openm;
@@ -749,14 +775,14 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                             const int nr = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(rems >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rems, 0u));
                             dEv = dE0 + __mul24(na - nr, dplus);
                         }
-                        ndraw_s += (uint32_t)__popcll(ballot64((uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)) & lanes_m);
+                        // draws of this step, counted per lane (lanes >= m are dropped at the end)
+                        ndraw_lane += (uint32_t)(dEv - 1) < (uint32_t)(dcut - 1) ? 1u : 0u;
                         if (accd) {
                             nacc_s += (uint32_t)__popcll(accd);
-                            if ((accd >> L) & 1ull) {
-                                cm ^= 1ull << (t - 1);
-                                Kc += dplus;
-                                Elane += dEv;
-                            }
+                            const int inA = (int)((accd >> L) & 1ull);   // this lane's site was flipped
+                            cm ^= (uint64_t)inA << (t - 1);
+                            Kc += __mul24(inA, dplus);
+                            Elane += __mul24(inA, dEv);
                             Yv[i + 1] += dY;
                             Yw[(t - 1) * 64 + L] = (uint16_t)Yv[i + 1];
                         }
@@ -813,6 +839,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 if (W > 1) bs[L * W + 1] = b1;
             }
         }
+        ndraw += (uint64_t)wave_sum64(lane_in ? (int64_t)ndraw_lane : 0);
         if (L == 0) {
             a.final_E[grep] = E;
             a.best_E[grep] = bestE;
