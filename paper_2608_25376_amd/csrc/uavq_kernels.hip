@@ -531,11 +531,14 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     const int nthr = blockDim.x, nwaves = nthr >> 6;
     const int Ts = a.thr_stride;
 
-    // LDS: two table rows | D | start-cell costs | per-wave travel rows
+    // LDS: two table rows | D | start-cell costs | signed cost rows | per-wave travel rows
     uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
     uint8_t *sD = smem + 8 * (size_t)Ts;
     uint8_t *sdep = sD + al16((size_t)m * m);
-    uint16_t *Yall = reinterpret_cast<uint16_t *>(sdep + al16((size_t)m));
+    // sDs[(0 or m) + c][L] = +D[c][L] or -D[c][L] (int16, rows of 64, 0 for L >= m): the
+    // change of Y_t when step t gains or loses cell c
+    int16_t *sDs = reinterpret_cast<int16_t *>(sdep + al16((size_t)m));
+    uint16_t *Yall = reinterpret_cast<uint16_t *>(sDs + 2 * 64 * (size_t)m);
     uint16_t *Yw = Yall + (size_t)wave * 64 * (m + 8);   // Y_t[c] at Yw[(t-1)*64 + c], t = 1..m+8
     __shared__ int s_first_sh;
     (void)nwaves;
@@ -546,6 +549,12 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         const int nD4 = (m * m + 15) >> 4, nd4 = (m + 15) >> 4;
         for (int i = threadIdx.x; i < nD4; i += nthr) reinterpret_cast<uint4 *>(sD)[i] = gD[i];
         for (int i = threadIdx.x; i < nd4; i += nthr) reinterpret_cast<uint4 *>(sdep)[i] = gdep[i];
+        const uint8_t *gDb = a.ws + d.d_off;
+        for (int i = threadIdx.x; i < 2 * 64 * m; i += nthr) {
+            const int c = (i >> 6) % m, l = i & 63;
+            const int v = l < m ? (int)gDb[c * m + l] : 0;
+            sDs[i] = (int16_t)(i < 64 * m ? v : -v);
+        }
     }
     const bool active = wave < it.nrep;
     const int r = it.rep0 + wave;
@@ -721,16 +730,15 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                         const int dplus = xb ? -twoP : twoP;    // change of dE per net 1 gained by step t
                         uint64_t openm = lanes_m, accd = 0;
                         int k = 0;                              // net 1s gained by step t so far
-                        int dY = 0, pdv = 0, psg = 0;           // cost-row entry of the last flip, added one step late
+                        int dY = 0, pdv = 0;                    // signed cost-row entry of the last flip, added one step late
                         // flip the first accepted site of accm
                         auto flip = [&](uint64_t accm) {
                             const int cstar = __builtin_ctzll(accm);
                             accd |= 1ull << cstar;
-                            dY += __mul24(psg, pdv);
-                            // lanes >= m read bytes past the row; their travel entries are never used
-                            pdv = sD[cstar * m + L];
-                            psg = ((rmask >> cstar) & 1ull) ? -1 : 1;   // +1: the flip sets x_{t,c*}
-                            k += psg;
+                            dY += pdv;
+                            const bool clears = (rmask >> cstar) & 1ull;   // the flip clears x_{t,c*}
+                            pdv = sDs[((clears ? m : 0) + cstar) * 64 + L];
+                            k += clears ? -1 : 1;
                             openm &= ~1ull << cstar;
                         };
                         bool walking = true;
@@ -766,7 +774,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                                 accm = ballot64(__mul24(k, dplus) < rel) & openm;
                             }
                         }
-                        dY += __mul24(psg, pdv);
+                        dY += pdv;
                         // the dE each site was visited with: dE0 plus dplus per net flip before it
                         int dEv = dE0;
                         if (accd) {
@@ -784,9 +792,12 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                             Kc += __mul24(inA, dplus);
                             Elane += __mul24(inA, dEv);
                             Yv[i + 1] += dY;
-                            Yw[(t - 1) * 64 + L] = (uint16_t)Yv[i + 1];
                         }
                     }
+                    // travel rows of the walked block, for the next sweep's reads
+#pragma unroll
+                    for (int i = 0; i < 4; i++)
+                        if (t0 + i <= m) Yw[(t0 + i - 1) * 64 + L] = (uint16_t)Yv[i + 1];
                 }
                 Yv0 = Yv[4];
                 Yv1 = Yv[5];
@@ -924,7 +935,8 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a) {
 // ------------------------------------------------------------- launchers --
 static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
     // per replica: travel rows of steps 1..m plus 8 boundary rows, 64 int16 each
-    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + (size_t)wpb * 64 * (m + 8) * 2;
+    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 256 * (size_t)m +
+           (size_t)wpb * 64 * (m + 8) * 2;
 }
 
 static size_t factored_lds_bytes(const uavq_plan *pl, int m) {
