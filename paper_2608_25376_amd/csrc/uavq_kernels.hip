@@ -84,6 +84,53 @@ __global__ __launch_bounds__(256) void k_init_states(KArgs a) {
 }
 
 // --------------------------------------------------------- factored sweep --
+// Acceptance cuts of four sites: for each, the least d >= 1 whose table entry thr(d) is
+// <= u, so that a flip with energy change dE is accepted exactly when dE < cut
+// (dE <= 0 always; 0 < dE < dcut iff u < thr(dE); thr(d) = 0 from dcut on).
+// The continuous threshold 2^32 exp(-d/T) drops to u at d = T ln 2 (32 -
+// log2 u); a guess half a step below that (e0 = 32 T ln 2 - 1/2) is the cut or
+// one short of it, which the entries d-1, d, d+1 settle.  Otherwise (never
+// seen: the guess is good to far better than half a step; or u = 2^32 - 1)
+// the table is walked.  The result depends on the table alone.  The LDS row
+// must hold valid entries up to index dcut + 1.
+__device__ __forceinline__ void accept_cuts(const uint4 &u4, float tl2, float e0, float dm1, int dcut,
+                                            const uint32_t *thr, int &cut0, int &cut1, int &cut2, int &cut3) {
+    const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
+    int d[4], cut[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const float e = fmaf(-tl2, __builtin_amdgcn_logf((float)u[i]), e0);   // u = 0: +inf
+        d[i] = (int)__builtin_amdgcn_fmed3f(e, 0.0f, dm1) + 1;                // 1..dcut
+    }
+    // all twelve entries are read unconditionally, so the reads issue together
+    uint32_t tm[4], t0[4], t1[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        tm[i] = thr[d[i] - 1];
+        t0[i] = thr[d[i]];
+        t1[i] = thr[d[i] + 1];
+    }
+    bool ok = true;
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        cut[i] = d[i] + (t0[i] > u[i] ? 1 : 0);
+        ok = ok & (tm[i] > u[i]) & (t1[i] <= u[i]);
+    }
+    if (ballot64(!ok)) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            int c = cut[i];
+            while (c < dcut && thr[c] > u[i]) c++;
+            while (c > 1 && thr[c - 1] <= u[i]) c--;
+            cut[i] = c;
+        }
+    }
+    cut0 = cut[0];
+    cut1 = cut[1];
+    cut2 = cut[2];
+    cut3 = cut[3];
+}
+
 template <int NJ>
 struct RowOps {
     // mask of the step held by lane lt of one chunk of the step masks
@@ -171,7 +218,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     __syncthreads();
     const int s_first = s_first_sh;
     if (s_first < a.S) {
-        const int n4 = (a.dcut[s_first] + 3) >> 2;
+        const int n4 = (a.dcut[s_first] + 2 + 3) >> 2;   // through index dcut + 1
         const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
         uint4 *dst = reinterpret_cast<uint4 *>(sthr + (s_first & 1) * Ts);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
@@ -237,6 +284,8 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     int64_t bestE = LLONG_MAX;
     int bestS = -1;
     uint64_t nacc = 0, ndraw = 0;
+    int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
+    uint32_t ndraw_lane = 0;   // draws of the lane's sites
     int dep[NJ];   // start-cell costs of this lane's cells (the fixed rows 0 and m+1)
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
@@ -248,7 +297,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         // next table row: loads issued now, stored to LDS after this sweep
         uint4 pre[KP];
         const bool has_next = s + 1 < a.S;
-        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 3) >> 2 : 0;
+        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 2 + 3) >> 2 : 0;
         const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
 #pragma unroll
         for (int k = 0; k < KP; k++) {
@@ -257,6 +306,8 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         }
         const uint32_t *thr = sthr + (s & 1) * Ts;
         const int dcut = uniform_load(a.dcut, s);
+        const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
+        const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
         if (active && s >= s0) {
             // Yp = Y_{t-1} (final), Yc = Y_t (updated on flips), Yn = Y_{t+1}, Ynn = Y_{t+2}
             int Yp[NJ], Yc[NJ], Yn[NJ], Ynn[NJ];
@@ -275,7 +326,9 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
                 for (int j = 0; j < NJ; j++) Yn[j] = d.closed ? dep[j] : 0;
             }
             int blk = -1;
-            uint4 u4[NJ];
+            uint32_t have_cut = 0;   // bit j: chunk j's cuts of the current block are known
+            uint32_t cutp[NJ][2];    // the block's cuts per chunk, two 16-bit values per word (cut <= dcut < 2^16)
+            uint32_t nacc_s = 0;
 #pragma unroll
             for (int jt = 0; jt < NJ; jt++)
                 for (int lt = 0; lt < 64; lt++) {
@@ -293,102 +346,136 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
 #pragma unroll
                         for (int j = 0; j < NJ; j++) Ynn[j] = d.closed ? dep[j] : 0;
                     }
-                    int R = Ops::popc(mc);
-                    int x[NJ], base[NJ];
+                    // ---- step t.  x, R_t and dE0 (dE against the state at the step
+                    // start) per lane and chunk; the walk then moves a uniform count
+                    // k of net 1s gained by the step, so every open site's dE is
+                    // dE0 + k dplus (cf. the m <= 64 sweep)
+                    const int hR0 = twoP * Ops::popc(mc);
+                    int dE0[NJ];
 #pragma unroll
                     for (int j = 0; j < NJ; j++) {
-                        x[j] = Ops::bit(mc, j, L);
-                        base[j] = Yp[j] + Yn[j] + twoP * (Cc[j] - 2 * x[j]) - twoP;
+                        const int xj = Ops::bit(mc, j, L);
+                        const int h = Yp[j] + Yn[j] + twoP * (Cc[j] - 2 * xj) - twoP + hR0;
+                        dE0[j] = xj ? -h : h;
                     }
-                    int start = 0;
-                    bool changed = false;
-                    while (true) {
-                        const int hR = twoP * R;
-                        bool acc[NJ], need[NJ];
-                        int dE[NJ];
-                        uint64_t needm[NJ];
-                        bool any_need = false;
+                    // change of dE per net 1 gained by step t (x read from the step mask)
+                    auto dplus = [&](int j) { return Ops::bit(mc, j, L) ? -twoP : twoP; };
+                    const int tb = (t - 1) >> 2, ti = (t - 1) & 3;
+                    if (blk != tb) {   // a new block of four steps: its words and cuts are not drawn yet
+                        blk = tb;
+                        have_cut = 0;
+                    }
+                    int k = 0, psg = 0;
+                    uint64_t accd[NJ];
+                    int dY[NJ], pd[NJ];   // travel-row change; cost-row entries of the last flip
 #pragma unroll
-                        for (int j = 0; j < NJ; j++) {
-                            const int c = 64 * j + L;
-                            const int h = base[j] + hR;
-                            dE[j] = x[j] ? -h : h;
-                            const bool valid = (c >= start) && (c < m);
-                            acc[j] = valid && dE[j] <= 0;
-                            need[j] = valid && dE[j] > 0 && dE[j] < dcut;
-                            needm[j] = ballot64(need[j]);
-                            any_need |= needm[j] != 0;
-                        }
-                        if (any_need) {
-                            const int tb = (t - 1) >> 2;
-                            if (blk != tb) {
-                                uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)tb;
-                                // keeps the generator inside this branch (computed only when a draw is due)
-                                asm volatile("" : "+v"(cbase));
+                    for (int j = 0; j < NJ; j++) {
+                        accd[j] = 0;
+                        dY[j] = 0;
+                        pd[j] = 0;
+                    }
+                    // flip the first accepted site of chunk j's mask am; its cost-row
+                    // entries are read now and added at the next flip
+                    auto flip = [&](int j, uint64_t am, uint64_t &openm) {
+                        const int Ls = __builtin_ctzll(am);
+                        accd[j] |= 1ull << Ls;
+                        const uint64_t rowj = ((uint64_t)mc[2 * j + 1] << 32) | (uint64_t)mc[2 * j];
+                        const bool clears = (rowj >> Ls) & 1ull;
 #pragma unroll
-                                for (int j = 0; j < NJ; j++)
-                                    u4[j] = philox(make_uint4(cbase + 64u * j, (uint32_t)s, (uint32_t)r, d.inst_id),
-                                                   a.seed, 0u);
-                                blk = tb;
+                        for (int jj = 0; jj < NJ; jj++) dY[jj] += __mul24(psg, pd[jj]);
+                        // lanes past m read bytes beyond the row (inside the allocation); unused
+                        const uint8_t *drow = sD + (64 * j + Ls) * m;
+#pragma unroll
+                        for (int jj = 0; jj < NJ; jj++) pd[jj] = drow[64 * jj + L];
+                        psg = clears ? -1 : 1;
+                        k += psg;
+                        openm &= ~1ull << Ls;
+                    };
+                    // a step with no valid site below the cut is finished: no accept, no draw
+                    int mnv = INT_MAX;
+#pragma unroll
+                    for (int j = 0; j < NJ; j++) mnv = min(mnv, 64 * j + L < m ? dE0[j] : INT_MAX);
+                    const bool cold = !ballot64(mnv < dcut);
+#pragma unroll
+                    for (int j = 0; j < NJ; j++) {
+                        if (cold || 64 * j >= m) break;
+                        uint64_t openm = m - 64 * j >= 64 ? ~0ull : ((1ull << (m - 64 * j)) - 1ull);
+                        bool walking = true;
+                        if (!((have_cut >> j) & 1u)) {
+                            // no exact cut yet: accept iff dE <= 0 while no open site of the
+                            // chunk needs a draw; then the chunk's words and cuts are drawn
+                            while (true) {
+                                const int dE = dE0[j] + __mul24(k, dplus(j));
+                                if (ballot64((uint32_t)(dE - 1) < (uint32_t)(dcut - 1)) & openm) {
+                                    have_cut |= 1u << j;
+                                    uint32_t cbase = (uint32_t)(64 * j + L) + 65536u * (uint32_t)tb;
+                                    asm volatile("" : "+v"(cbase));   // generator stays inside this branch
+                                    const uint4 u4 = philox(make_uint4(cbase, (uint32_t)s, (uint32_t)r, d.inst_id),
+                                                            a.seed, 0u);
+                                    int c0, c1, c2, c3;
+                                    accept_cuts(u4, tl2, e0, dm1, dcut, thr, c0, c1, c2, c3);
+                                    cutp[j][0] = (uint32_t)c0 | ((uint32_t)c1 << 16);
+                                    cutp[j][1] = (uint32_t)c2 | ((uint32_t)c3 << 16);
+                                    break;
+                                }
+                                const uint64_t am = ballot64(dE <= 0) & openm;
+                                if (!am) {
+                                    walking = false;
+                                    break;
+                                }
+                                flip(j, am, openm);
                             }
-                            const int wsel = (t - 1) & 3;
-#pragma unroll
-                            for (int j = 0; j < NJ; j++)
-                                if (need[j]) acc[j] = pick4(u4[j], wsel) < thr[dE[j]];
                         }
-                        int cstar = -1;
-#pragma unroll
-                        for (int j = 0; j < NJ; j++) {
-                            const uint64_t am = ballot64(acc[j]);
-                            if (cstar < 0 && am) cstar = 64 * j + __builtin_ctzll(am);
+                        if (walking) {
+                            const int cut = (int)((cutp[j][ti >> 1] >> (16 * (ti & 1))) & 0xffffu);
+                            const int rel = cut - dE0[j];   // accept iff k dplus < cut - dE0
+                            uint64_t am = ballot64(__mul24(k, dplus(j)) < rel) & openm;
+                            while (am) {
+                                flip(j, am, openm);
+                                am = ballot64(__mul24(k, dplus(j)) < rel) & openm;
+                            }
                         }
-                        if (cstar < 0) {
+                    }
+                    bool any = false;
 #pragma unroll
-                            for (int j = 0; j < NJ; j++) ndraw += __popcll(needm[j]);
-                            break;
-                        }
-                        // draws taken at sites start .. cstar
-                        const int jstar = cstar >> 6, Lstar = cstar & 63;
-#pragma unroll
-                        for (int j = 0; j < NJ; j++) {
-                            if (j < jstar) ndraw += __popcll(needm[j]);
-                            else if (j == jstar)
-                                ndraw += __popcll(needm[j] & (Lstar == 63 ? ~0ull : ((2ull << Lstar) - 1ull)));
-                        }
-                        // apply the flip of (t, cstar)
-                        const int wstar = cstar >> 5;
-                        const uint32_t bstar_bit = 1u << (cstar & 31);
-                        int xs = 0;
-#pragma unroll
-                        for (int w = 0; w < 2 * NJ; w++)
-                            if (w == wstar) xs = (mc[w] & bstar_bit) ? 1 : 0;
-                        const int sign = xs ? -1 : 1;
-                        int bstar = 0;
+                    for (int j = 0; j < NJ; j++) any |= accd[j] != 0;
+                    if (cold) {
+                    } else if (!any) {
+                        // no flip: every site was visited with its dE0
 #pragma unroll
                         for (int j = 0; j < NJ; j++)
-                            if (j == jstar) bstar = __builtin_amdgcn_readlane(base[j], Lstar);
-                        const int hstar = bstar + hR;
-                        E += (int64_t)(xs ? -hstar : hstar);
-                        nacc++;
+                            ndraw_lane += (64 * j + L < m && (uint32_t)(dE0[j] - 1) < (uint32_t)(dcut - 1)) ? 1u : 0u;
+                    } else {
 #pragma unroll
-                        for (int w = 0; w < 2 * NJ; w++)
-                            if (w == wstar) mc[w] ^= bstar_bit;
-                        R += sign;
-                        changed = true;
-                        const uint8_t *drow = sD + cstar * m;
+                        for (int jj = 0; jj < NJ; jj++) dY[jj] += __mul24(psg, pd[jj]);
+                        // visit-time dE of every site (dE0 plus dplus per net flip before it
+                        // in site order), then draws, energy, counts and the step mask
+                        int nab = 0, nrb = 0;   // adds / removes in earlier chunks
 #pragma unroll
                         for (int j = 0; j < NJ; j++) {
-                            const int c = 64 * j + L;
-                            if (j == jstar && L == Lstar) {
-                                Cc[j] += sign;
-                                x[j] ^= 1;
-                            }
-                            if (c < m) Yc[j] += sign * (int)drow[c];
+                            const uint64_t rowj = ((uint64_t)mc[2 * j + 1] << 32) | (uint64_t)mc[2 * j];
+                            const uint64_t adds = accd[j] & ~rowj, rems = accd[j] & rowj;
+                            const int na = nab + (int)__builtin_amdgcn_mbcnt_hi(
+                                                     (uint32_t)(adds >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)adds, 0u));
+                            const int nr = nrb + (int)__builtin_amdgcn_mbcnt_hi(
+                                                     (uint32_t)(rems >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)rems, 0u));
+                            const int dEv = dE0[j] + __mul24(na - nr, dplus(j));
+                            ndraw_lane += (64 * j + L < m && (uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)) ? 1u : 0u;
+                            const int inA = (int)((accd[j] >> L) & 1ull);
+                            Elane += __mul24(inA, dEv);
+                            Cc[j] += Ops::bit(mc, j, L) ? -inA : inA;
+                            Yc[j] += dY[j];
+                            nab += (int)__popcll(adds);
+                            nrb += (int)__popcll(rems);
+                            nacc_s += (uint32_t)__popcll(accd[j]);
                         }
-                        start = cstar + 1;
-                        if (start >= m) break;
+#pragma unroll
+                        for (int j = 0; j < NJ; j++) {
+                            mc[2 * j] ^= (uint32_t)accd[j];
+                            mc[2 * j + 1] ^= (uint32_t)(accd[j] >> 32);
+                        }
+                        Ops::write(rm[jt], lt, mc, L);
                     }
-                    if (changed) Ops::write(rm[jt], lt, mc, L);
 #pragma unroll
                     for (int j = 0; j < NJ; j++) {
                         Yp[j] = Yc[j];
@@ -401,6 +488,11 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
                         mn[w] = mnn[w];
                     }
                 }
+            nacc += nacc_s;
+            if (nacc_s) {
+                E += wave_sum64((int64_t)Elane);
+                Elane = 0;
+            }
             if (E < bestE) {
                 bestE = E;
                 bestS = s;
@@ -436,6 +528,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
                 for (int w = 0; w < 2 * NJ; w++)
                     if (w < W) st[(t - 1) * W + w] = rm[j][w];
         }
+        ndraw += (uint64_t)wave_sum64((int64_t)ndraw_lane);
         if (L == 0) {
             a.final_E[grep] = E;
             a.best_E[grep] = bestE;
@@ -468,53 +561,6 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
     }
 }
 
-
-// Acceptance cuts of four sites: for each, the least d >= 1 whose table entry thr(d) is
-// <= u, so that a flip with energy change dE is accepted exactly when dE < cut
-// (dE <= 0 always; 0 < dE < dcut iff u < thr(dE); thr(d) = 0 from dcut on).
-// The continuous threshold 2^32 exp(-d/T) drops to u at d = T ln 2 (32 -
-// log2 u); a guess half a step below that (e0 = 32 T ln 2 - 1/2) is the cut or
-// one short of it, which the entries d-1, d, d+1 settle.  Otherwise (never
-// seen: the guess is good to far better than half a step; or u = 2^32 - 1)
-// the table is walked.  The result depends on the table alone.  The LDS row
-// must hold valid entries up to index dcut + 1.
-__device__ __forceinline__ void accept_cuts(const uint4 &u4, float tl2, float e0, float dm1, int dcut,
-                                            const uint32_t *thr, int &cut0, int &cut1, int &cut2, int &cut3) {
-    const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
-    int d[4], cut[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const float e = fmaf(-tl2, __builtin_amdgcn_logf((float)u[i]), e0);   // u = 0: +inf
-        d[i] = (int)__builtin_amdgcn_fmed3f(e, 0.0f, dm1) + 1;                // 1..dcut
-    }
-    // all twelve entries are read unconditionally, so the reads issue together
-    uint32_t tm[4], t0[4], t1[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        tm[i] = thr[d[i] - 1];
-        t0[i] = thr[d[i]];
-        t1[i] = thr[d[i] + 1];
-    }
-    bool ok = true;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        cut[i] = d[i] + (t0[i] > u[i] ? 1 : 0);
-        ok = ok & (tm[i] > u[i]) & (t1[i] <= u[i]);
-    }
-    if (ballot64(!ok)) {
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            int c = cut[i];
-            while (c < dcut && thr[c] > u[i]) c++;
-            while (c > 1 && thr[c - 1] <= u[i]) c--;
-            cut[i] = c;
-        }
-    }
-    cut0 = cut[0];
-    cut1 = cut[1];
-    cut2 = cut[2];
-    cut3 = cut[3];
-}
 
 // ------------------------------------------------ sweep, LDS-resident rows --
 // Variant for m <= 64 (one cell per lane): lane c keeps its cell's column of
@@ -940,7 +986,8 @@ static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
 }
 
 static size_t factored_lds_bytes(const uavq_plan *pl, int m) {
-    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m);
+    // + 64: cost-row reads of lanes past m run up to 63 bytes beyond D
+    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64;
 }
 
 static int class_mmax(const uavq_plan *pl, int cls) {
