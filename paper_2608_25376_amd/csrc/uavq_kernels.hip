@@ -22,7 +22,7 @@
 //
 // Replica state lives in registers: lane L holds the cell masks of steps
 // L + 1 + 64 j (bits = cells) and the occupation count of cells L + 64 j.  The
-// cost matrix D (bytes), the start-cell costs and a double-buffered row of the
+// cost matrix D (bytes), the start-cell costs and a single row of the
 // acceptance table live in LDS and are shared by the block's replicas.
 #include <hip/hip_runtime.h>
 
@@ -194,9 +194,9 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     const int nthr = blockDim.x;
     const int Ts = a.thr_stride;   // row stride of the acceptance table, a multiple of 4
 
-    // LDS: two acceptance-table rows | D (m*m bytes) | start-cell costs (m bytes)
+    // LDS: the acceptance-table row | D (m*m bytes) | start-cell costs (m bytes)
     uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
-    uint8_t *sD = smem + 8 * (size_t)Ts;
+    uint8_t *sD = smem + 4 * (size_t)Ts;
     uint8_t *sdep = sD + al16((size_t)m * m);
     __shared__ int s_first_sh;
 
@@ -220,7 +220,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     if (s_first < a.S) {
         const int n4 = (a.dcut[s_first] + 2 + 3) >> 2;   // through index dcut + 1
         const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
-        uint4 *dst = reinterpret_cast<uint4 *>(sthr + (s_first & 1) * Ts);
+        uint4 *dst = reinterpret_cast<uint4 *>(sthr);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
     }
     __syncthreads();
@@ -304,7 +304,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
             const int i = threadIdx.x + k * nthr;
             pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
         }
-        const uint32_t *thr = sthr + (s & 1) * Ts;
+        const uint32_t *thr = sthr;
         const int dcut = uniform_load(a.dcut, s);
         const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
@@ -507,8 +507,11 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
                 }
             }
         }
+        // one table row in LDS: every wave is done with row s before row s + 1
+        // (prefetched into registers during the sweep) replaces it
+        __syncthreads();
         if (has_next) {
-            uint4 *dst = reinterpret_cast<uint4 *>(sthr + ((s + 1) & 1) * Ts);
+            uint4 *dst = reinterpret_cast<uint4 *>(sthr);
 #pragma unroll
             for (int k = 0; k < KP; k++) {
                 const int i = threadIdx.x + k * nthr;
@@ -577,9 +580,9 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     const int nthr = blockDim.x, nwaves = nthr >> 6;
     const int Ts = a.thr_stride;
 
-    // LDS: two table rows | D | start-cell costs | signed cost rows | per-wave travel rows
+    // LDS: the table row | D | start-cell costs | signed cost rows | per-wave travel rows
     uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
-    uint8_t *sD = smem + 8 * (size_t)Ts;
+    uint8_t *sD = smem + 4 * (size_t)Ts;
     uint8_t *sdep = sD + al16((size_t)m * m);
     // sDs[(0 or m) + c][L] = +D[c][L] or -D[c][L] (int16, rows of 64, 0 for L >= m): the
     // change of Y_t when step t gains or loses cell c
@@ -614,7 +617,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     if (s_first < a.S) {
         const int n4 = (uniform_load(a.dcut, s_first) + 2 + 3) >> 2;   // through index dcut + 1
         const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
-        uint4 *dst = reinterpret_cast<uint4 *>(sthr + (s_first & 1) * Ts);
+        uint4 *dst = reinterpret_cast<uint4 *>(sthr);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
     }
     __syncthreads();
@@ -685,7 +688,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             const int i = threadIdx.x + k * nthr;
             pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
         }
-        const uint32_t *thr = sthr + (s & 1) * Ts;
+        const uint32_t *thr = sthr;
         const int dcut = uniform_load(a.dcut, s);
         const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
@@ -862,8 +865,11 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 bestcm = cm;
             }
         }
+        // one table row in LDS: every wave is done with row s before row s + 1
+        // (prefetched into registers during the sweep) replaces it
+        __syncthreads();
         if (has_next) {
-            uint4 *dst = reinterpret_cast<uint4 *>(sthr + ((s + 1) & 1) * Ts);
+            uint4 *dst = reinterpret_cast<uint4 *>(sthr);
 #pragma unroll
             for (int k = 0; k < KP; k++) {
                 const int i = threadIdx.x + k * nthr;
@@ -981,13 +987,13 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a) {
 // ------------------------------------------------------------- launchers --
 static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
     // per replica: travel rows of steps 1..m plus 8 boundary rows, 64 int16 each
-    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 256 * (size_t)m +
+    return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 256 * (size_t)m +
            (size_t)wpb * 64 * (m + 8) * 2;
 }
 
 static size_t factored_lds_bytes(const uavq_plan *pl, int m) {
     // + 64: cost-row reads of lanes past m run up to 63 bytes beyond D
-    return 8 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64;
+    return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64;
 }
 
 static int class_mmax(const uavq_plan *pl, int cls) {
