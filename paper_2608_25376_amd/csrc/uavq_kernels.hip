@@ -1385,15 +1385,20 @@ int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *ins
     const std::string key = tune_key(q, n_inst, p, cu);
     if (cache_path && cache_lookup(cache_path, key, out)) return UAVQ_OK;
 
+    // Chunk classes launch one after another, so each class's shape is chosen
+    // on its own kernel's time (events around each class's launch); the
+    // variant only concerns class 1.
     const int wpbs[] = {1, 2, 4, 8, 16};
     const uint32_t variants[] = {0u, UAVQ_VARIANT_ROWMASK};
     hipStream_t st = nullptr;
     UAVQ_HIP(hipStreamCreate(&st));
-    hipEvent_t e0, e1;
-    UAVQ_HIP(hipEventCreate(&e0));
-    UAVQ_HIP(hipEventCreate(&e1));
-    uavq_tune best{};
-    best.trial_ms = 1e30f;
+    float best_cls[kMaxChunks + 1];
+    int best_wpb[kMaxChunks + 1];
+    uint32_t best_var = 0u;
+    for (int c = 0; c <= kMaxChunks; c++) {
+        best_cls[c] = 1e30f;
+        best_wpb[c] = 4;
+    }
     int rc = UAVQ_OK;
     for (uint32_t var : variants) {
         for (int wpb : wpbs) {
@@ -1428,33 +1433,55 @@ int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *ins
                 o.inst_best_replica = (int32_t *)b;        b += (size_t)n_inst * 4;
                 o.inst_best_sweep = (int32_t *)b;          b += (size_t)n_inst * 4;
                 o.inst_best_state = (uint32_t *)b;
-                if (uavq_anneal_batch(pl, ws, pl->ws_bytes, nullptr, &o, st) == UAVQ_OK &&
+                float cls_ms[kMaxChunks + 1];
+                for (int c = 0; c <= kMaxChunks; c++) cls_ms[c] = 1e30f;
+                if (uavq_plan_set_timing(pl, 1) == UAVQ_OK &&
+                    uavq_anneal_batch(pl, ws, pl->ws_bytes, nullptr, &o, st) == UAVQ_OK &&
                     hipStreamSynchronize(st) == hipSuccess) {
-                    float acc[3];
                     bool good = true;
                     for (int rep = 0; rep < 3 && good; rep++) {
-                        good = hipEventRecord(e0, st) == hipSuccess &&
-                               uavq_anneal_batch(pl, ws, pl->ws_bytes, nullptr, &o, st) == UAVQ_OK &&
-                               hipEventRecord(e1, st) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-                               hipEventElapsedTime(&acc[rep], e0, e1) == hipSuccess;
+                        good = uavq_anneal_batch(pl, ws, pl->ws_bytes, nullptr, &o, st) == UAVQ_OK &&
+                               hipStreamSynchronize(st) == hipSuccess;
+                        for (int c = 1; c <= kMaxChunks && good; c++) {
+                            if (pl->class_begin[c + 1] <= pl->class_begin[c]) continue;
+                            float e = 0.0f;
+                            good = hipEventElapsedTime(&e, (hipEvent_t)pl->ev[2 * c], (hipEvent_t)pl->ev[2 * c + 1]) ==
+                                   hipSuccess;
+                            if (good) cls_ms[c] = std::min(cls_ms[c], e);
+                        }
                     }
-                    if (good) ms = std::min(acc[0], std::min(acc[1], acc[2]));
+                    if (good) ms = 0.0f;
+                }
+                if (ms == 0.0f) {
+                    for (int c = 1; c <= kMaxChunks; c++) {
+                        if (c > 1 && var != 0u) continue;   // the variant changes class 1 only
+                        if (cls_ms[c] < best_cls[c]) {
+                            best_cls[c] = cls_ms[c];
+                            best_wpb[c] = wpb;
+                            if (c == 1) best_var = var;
+                        }
+                    }
                 }
             }
             (void)hipStreamSynchronize(st);
             if (ws) (void)hipFree(ws);
             if (buf) (void)hipFree(buf);
             uavq_plan_free(pl);
-            if (ms < best.trial_ms) {
-                best = t;
-                best.trial_ms = ms;
-            }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(st);
-    if (best.trial_ms >= 1e30f) return set_error(UAVQ_EHIP, "autotune: no candidate ran");
+    uavq_tune best{};
+    best.trial_ms = 0.0f;
+    bool any = false;
+    for (int c = 1; c <= kMaxChunks; c++) {
+        best.waves_per_block[c] = best_wpb[c];
+        if (best_cls[c] < 1e30f) {
+            best.trial_ms += best_cls[c];
+            any = true;
+        }
+    }
+    best.variant_flags = best_var;
+    if (!any) return set_error(UAVQ_EHIP, "autotune: no candidate ran");
     *out = best;
     if (cache_path) cache_store(cache_path, key, best);
     return rc;
