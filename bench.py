@@ -46,7 +46,92 @@ def parse():
     ap.add_argument("--cpu-replicas", type=int, default=0, help="oracle sample size (0 = auto)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (reference run for the HBM byte counters)")
+    ap.add_argument("--aux", action="store_true",
+                    help="instead: time the MFMA energy refresh and the warm-start network step (one JSON line each)")
     return ap.parse_args()
+
+
+PEAK_INT8_OPS = 5.0e15      # MI355X dense int8 MFMA
+PEAK_BF16_FLOPS = 2.5e15    # MI355X dense bf16 MFMA
+
+
+def _time_ms(fn, reps):
+    import torch
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def aux_measurements(args):
+    """The two MFMA users besides the sweep: the int8 energy refresh (Z = X D
+    per state, two byte limbs, int32 accumulation) at the 12x12 and 8x8 sizes,
+    and one forward+backward step of the warm-start network (bf16 operands,
+    fp32 accumulation) on a batch of 32 fields of 10x10, eager and replayed
+    from a captured HIP graph."""
+    import numpy as np
+    import torch
+    from paper_2608_25376_amd import inputs, uavq
+    for name in ("grid12x12", "grid8x8_nofly0.1"):
+        w = inputs.workload(name)
+        g = w.grids[0]
+        q = uavq.qubo_build(g.rows, g.cols, nofly=g.nofly)
+        rng = np.random.default_rng(7)
+        X = np.zeros((w.replicas, q.m, q.m), np.uint8)
+        for r in range(w.replicas):
+            X[r, np.arange(q.m), rng.permutation(q.m)] = 1
+        d_states = torch.from_numpy(uavq.pack_states(X.reshape(w.replicas, -1), q.m).view(np.int32)).cuda()
+        d_E = torch.empty(w.replicas, dtype=torch.int64, device="cuda")
+        ms = _time_ms(lambda: uavq.energy_eval_dev(q, d_states, d_E), 20)
+        ops = 4.0 * q.m ** 3 * w.replicas   # 2 limbs x m^3 MACs x 2 ops per state
+        print(json.dumps({"metric": "int8 MFMA ops/s (energy refresh)", "value": ops / (ms * 1e-3), "unit": "ops/s",
+                          "kernel": "k_energy_refresh", "config": {"workload": name, "m": q.m, "states": w.replicas},
+                          "ms_per_call": ms, "ops_per_call": ops, "peak": PEAK_INT8_OPS,
+                          "frac": ops / (ms * 1e-3) / PEAK_INT8_OPS}), flush=True)
+    # warm-start network: 32 fields of 10x10 (about 85 free cells each)
+    from paper_2608_25376_amd import warmstart
+    grids = inputs.batch(32, seed=1, side=10, density_hi=0.2, first_id=10000)
+    feats, steps, labels = [], [], []
+    for gr in grids:
+        qq = uavq.qubo_build(gr.rows, gr.cols, nofly=gr.nofly)
+        feats.append(uavq.mlp_features(qq))
+        steps.append(np.full(qq.m, qq.m, np.int32))
+        labels.append(np.random.default_rng(gr.inst_id).permutation(qq.m).astype(np.int32))
+    Xf = torch.from_numpy(np.concatenate(feats)).cuda()
+    Ms = torch.from_numpy(np.concatenate(steps)).cuda()
+    Lb = torch.from_numpy(np.concatenate(labels)).cuda()
+    rows = Xf.shape[0]
+    net = uavq.Mlp(warmstart.init_params(1))
+    eager_ms = _time_ms(lambda: net.loss_grad(Xf, Ms, Lb), 50)
+    g_eager = net.grad.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        net.loss_grad(Xf, Ms, Lb, stream=side)   # workspace allocated outside the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        net.loss_grad(Xf, Ms, Lb, stream=torch.cuda.current_stream())
+    same = True
+    for _ in range(3):                            # every replay equals the eager step
+        net.grad.zero_()
+        graph.replay()
+        torch.cuda.synchronize()
+        same &= bool(torch.equal(net.grad, g_eager))
+    graph_ms = _time_ms(graph.replay, 50)
+    flops = 3 * 2.0 * rows * (16 * 128 + 128 * 128 + 128 * 128)   # forward + two backward products per layer
+    print(json.dumps({"metric": "bf16 MFMA FLOP/s (warm-start network forward+backward)",
+                      "value": flops / (graph_ms * 1e-3), "unit": "FLOP/s", "kernel": "k_gemm_bf16 + k_softmax_ce",
+                      "config": {"rows": rows, "fields": 32, "params": uavq.mlp_param_count()},
+                      "eager_ms": eager_ms, "graph_ms": graph_ms, "graph_equals_eager": same,
+                      "flops_per_step": flops, "peak": PEAK_BF16_FLOPS,
+                      "frac": flops / (graph_ms * 1e-3) / PEAK_BF16_FLOPS}), flush=True)
 
 
 # Sources of the sweep kernels; an HBM-traffic record applies only to the
@@ -128,6 +213,9 @@ def main():
     torch.cuda.set_device(0)
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
+        return
+    if args.aux:
+        aux_measurements(args)
         return
     w = inputs.workload(args.workload)
     dense = args.kernel == "dense"

@@ -48,27 +48,34 @@ struct GemmArgs {
     int32_t M, N, K;
     int32_t relu_a;         // apply max(0, .) to A on load
     int32_t accumulate;     // C += result
+    int32_t kchunk;         // > 0: split K into chunks of this length; chunk q's partial product goes to
+    int64_t c_chunk;        //      C + q * c_chunk (no bias, mask or accumulation)
 };
 
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
     const int tilesM = (g.M + 15) >> 4, tilesN = (g.N + 15) >> 4;
+    const int nchunk = g.kchunk > 0 ? (g.K + g.kchunk - 1) / g.kchunk : 1;
     const int64_t tile = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (tile >= (int64_t)tilesM * tilesN) return;
-    const int tm = (int)(tile % tilesM), tn = (int)(tile / tilesM);
+    if (tile >= (int64_t)tilesM * tilesN * nchunk) return;
+    const int64_t tmn = tile % ((int64_t)tilesM * tilesN);
+    const int q = (int)(tile / ((int64_t)tilesM * tilesN));
+    const int tm = (int)(tmn % tilesM), tn = (int)(tmn / tilesM);
     const int ai = 16 * tm + li, bn = 16 * tn + li;
+    const int kbeg = g.kchunk > 0 ? q * g.kchunk : 0;
+    const int kend = g.kchunk > 0 ? min(g.K, kbeg + g.kchunk) : g.K;
     v4f acc = {0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < g.K; k0 += 16) {
+    for (int k0 = kbeg; k0 < kend; k0 += 16) {
         v4s av, bv;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
             const int k = k0 + 4 * lg + j;
             float a = 0.f, b = 0.f;
-            if (ai < g.M && k < g.K) {
+            if (ai < g.M && k < kend) {
                 a = g.A[ai * g.a_si + k * g.a_sk];
                 if (g.relu_a) a = fmaxf(a, 0.f);
             }
-            if (bn < g.N && k < g.K) b = g.B[k * g.b_sk + bn * g.b_sn];
+            if (bn < g.N && k < kend) b = g.B[k * g.b_sk + bn * g.b_sn];
             av[j] = (short)bf16_bits(a);
             bv[j] = (short)bf16_bits(b);
         }
@@ -79,6 +86,10 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         const int i = 16 * tm + 4 * lg + v;
         if (i < g.M && bn < g.N) {
             float c = acc[v];
+            if (g.kchunk > 0) {
+                g.C[q * g.c_chunk + i * g.ldc + bn] = c;
+                continue;
+            }
             if (g.bias) c += g.bias[bn];
             if (g.zmask && !(g.zmask[i * g.ldz + bn] > 0.f)) c = 0.f;
             float *dst = g.C + i * g.ldc + bn;
@@ -118,11 +129,23 @@ __global__ __launch_bounds__(256) void k_softmax_ce(const float *Z, const int32_
 }
 
 // column sums of G [rows x n] (bias gradients); one thread per column
-__global__ void k_colsum(const float *G, int rows, int n, float *out) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+// Column sums of G[rows][n] in chunks of rchunk rows: block q writes the sums
+// of its rows to part[q][n].
+__global__ void k_colsum(const float *G, int rows, int n, int rchunk, float *part) {
+    const int j = threadIdx.x, q = blockIdx.x;
+    if (j >= n) return;
+    const int i1 = min(rows, (q + 1) * rchunk);
+    float s = 0.f;
+    for (int i = q * rchunk; i < i1; i++) s += G[(int64_t)i * n + j];
+    part[(int64_t)q * n + j] = s;
+}
+
+// out[j] = sum over q = 0..nq-1 (in this order) of part[q * stride + j]
+__global__ void k_sum_parts(const float *part, int nq, int64_t stride, int64_t n, float *out) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     float s = 0.f;
-    for (int i = 0; i < rows; i++) s += G[(int64_t)i * n + j];
+    for (int q = 0; q < nq; q++) s += part[q * stride + j];
     out[j] = s;
 }
 
@@ -220,8 +243,10 @@ int uavq_mlp_param_count(void) { return 16 * 128 + 128 + 128 * 128 + 128 + 128 *
 
 int uavq_mlp_workspace_bytes(int32_t rows, size_t *bytes) {
     if (rows < 0 || !bytes) return set_error(UAVQ_EINVAL, "mlp_workspace_bytes: bad argument");
-    // Z1, Z2, Z3, P, G3, G2, G1 (rows x 128 each) + per-row loss
-    *bytes = (size_t)rows * 128 * 4 * 7 + (size_t)rows * 4 + 256;
+    // Z1, Z2, Z3, P, G3, G2, G1 (rows x 128 each) + per-row loss + partial products of
+    // the row-split gradient reductions (chunks of 128 rows)
+    const size_t nq = ((size_t)rows + 127) / 128;
+    *bytes = (size_t)rows * 128 * 4 * 7 + (size_t)rows * 4 + 256 + nq * 128 * 128 * 4 + nq * 128 * 4 + 256;
     return UAVQ_OK;
 }
 
@@ -229,9 +254,36 @@ static int gemm(hipStream_t st, const float *A, int64_t a_si, int64_t a_sk, cons
                 float *C, int64_t ldc, int M, int N, int K, const float *bias, const float *zmask, int64_t ldz,
                 int relu_a, int accumulate) {
     if (M <= 0 || N <= 0) return UAVQ_OK;
-    GemmArgs g{A, a_si, a_sk, B, b_sk, b_sn, C, ldc, bias, zmask, ldz, M, N, K, relu_a, accumulate};
+    GemmArgs g{A, a_si, a_sk, B, b_sk, b_sn, C, ldc, bias, zmask, ldz, M, N, K, relu_a, accumulate, 0, 0};
     const int64_t tiles = (int64_t)((M + 15) / 16) * ((N + 15) / 16);
     hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, g);
+    UAVQ_HIP(hipGetLastError());
+    return UAVQ_OK;
+}
+
+// C[M][N] = A^T-style product over a long K (the rows of a batch), split into
+// chunks of 128 whose partial tiles are summed in chunk order: deterministic,
+// and enough waves for the weight gradients.
+static int gemm_rows(hipStream_t st, const float *A, int64_t a_si, int64_t a_sk, const float *B, int64_t b_sk,
+                     int64_t b_sn, float *C, int M, int N, int K, int relu_a, float *part) {
+    if (M <= 0 || N <= 0) return UAVQ_OK;
+    const int nq = (K + 127) / 128;
+    GemmArgs g{A, a_si, a_sk, B, b_sk, b_sn, part, N, nullptr, nullptr, 0, M, N, K, relu_a, 0, 128,
+               (int64_t)M * N};
+    const int64_t tiles = (int64_t)((M + 15) / 16) * ((N + 15) / 16) * nq;
+    hipLaunchKernelGGL(k_gemm_bf16, dim3((unsigned)((tiles + 3) / 4)), dim3(256), 0, st, g);
+    UAVQ_HIP(hipGetLastError());
+    const int64_t n = (int64_t)M * N;
+    hipLaunchKernelGGL(k_sum_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part, nq, n, n, C);
+    UAVQ_HIP(hipGetLastError());
+    return UAVQ_OK;
+}
+
+static int colsum_rows(hipStream_t st, const float *G, int rows, float *out, float *part) {
+    const int nq = (rows + 127) / 128;
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)nq), dim3(128), 0, st, G, rows, 128, 128, part);
+    UAVQ_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(128), 0, st, part, nq, (int64_t)128, (int64_t)128, out);
     UAVQ_HIP(hipGetLastError());
     return UAVQ_OK;
 }
@@ -285,6 +337,9 @@ int uavq_mlp_loss_grad(const float *d_params, const float *d_X, const int32_t *d
     const size_t L = (size_t)rows * 128;
     float *Z1 = (float *)d_ws, *Z2 = Z1 + L, *Z3 = Z2 + L, *P = Z3 + L, *G3 = P + L, *G2 = G3 + L, *G1 = G2 + L;
     float *rl = G1 + L;
+    const size_t nq = ((size_t)rows + 127) / 128;
+    float *gpart = (float *)(((uintptr_t)(rl + rows) + 255) & ~(uintptr_t)255);   // nq x 128 x 128
+    float *cpart = gpart + nq * 128 * 128;                                          // nq x 128
     int rc = forward(d_params, d_X, rows, Z1, Z2, Z3, st);
     if (rc) return rc;
     const float scale = 1.0f / (float)rows;
@@ -296,17 +351,16 @@ int uavq_mlp_loss_grad(const float *d_params, const float *d_X, const int32_t *d
     float *gW1 = d_grad, *gb1 = gW1 + 16 * 128, *gW2 = gb1 + 128, *gb2 = gW2 + 128 * 128, *gW3 = gb2 + 128,
           *gb3 = gW3 + 128 * 128;
     // layer 3: dW3 = relu(Z2)^T G3, db3 = colsum G3, G2 = (G3 W3^T) * [Z2 > 0]
-    if ((rc = gemm(st, Z2, 1, 128, G3, 128, 1, gW3, 128, 128, 128, rows, nullptr, nullptr, 0, 1, 0))) return rc;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, st, G3, rows, 128, gb3);
+    if ((rc = gemm_rows(st, Z2, 1, 128, G3, 128, 1, gW3, 128, 128, rows, 1, gpart))) return rc;
+    if ((rc = colsum_rows(st, G3, rows, gb3, cpart))) return rc;
     if ((rc = gemm(st, G3, 128, 1, w.W3, 1, 128, G2, 128, rows, 128, 128, nullptr, Z2, 128, 0, 0))) return rc;
     // layer 2
-    if ((rc = gemm(st, Z1, 1, 128, G2, 128, 1, gW2, 128, 128, 128, rows, nullptr, nullptr, 0, 1, 0))) return rc;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, st, G2, rows, 128, gb2);
+    if ((rc = gemm_rows(st, Z1, 1, 128, G2, 128, 1, gW2, 128, 128, rows, 1, gpart))) return rc;
+    if ((rc = colsum_rows(st, G2, rows, gb2, cpart))) return rc;
     if ((rc = gemm(st, G2, 128, 1, w.W2, 1, 128, G1, 128, rows, 128, 128, nullptr, Z1, 128, 0, 0))) return rc;
     // layer 1
-    if ((rc = gemm(st, d_X, 1, 16, G1, 128, 1, gW1, 128, 16, 128, rows, nullptr, nullptr, 0, 0, 0))) return rc;
-    hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, st, G1, rows, 128, gb1);
-    UAVQ_HIP(hipGetLastError());
+    if ((rc = gemm_rows(st, d_X, 1, 16, G1, 128, 1, gW1, 16, 128, rows, 0, gpart))) return rc;
+    if ((rc = colsum_rows(st, G1, rows, gb1, cpart))) return rc;
     return UAVQ_OK;
 }
 
