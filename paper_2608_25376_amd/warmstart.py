@@ -79,17 +79,25 @@ def canonical(order):
     return order if order[0] < order[-1] else order[::-1]
 
 
-def label_data(grids, R, S, T0, T1, seed):
-    qs = _qubos(grids)
-    plan, out, ms = _anneal(qs, grids, R, S, T0, T1, seed)
-    data = []
-    for (E, order), q in zip(best_tours(plan, qs, out), qs):
-        if order is None:
-            continue
-        order = canonical(order)
-        labels = np.empty(q.m, np.int32)
-        labels[order] = np.arange(q.m, dtype=np.int32)     # cell -> step (0-based)
-        data.append((uavq.mlp_features(q), labels, q.m))
+def label_data(grids, R, S, T0, T1, seed, chunk=200, log=None):
+    """Best tours of plain annealing, in launches of ``chunk`` instances (an
+    instance's result does not depend on the batch it runs in)."""
+    data, ms = [], 0.0
+    for c0 in range(0, len(grids), chunk):
+        part = grids[c0:c0 + chunk]
+        qs = _qubos(part)
+        plan, out, dt = _anneal(qs, part, R, S, T0, T1, seed)
+        ms += dt
+        for (E, order), q in zip(best_tours(plan, qs, out), qs):
+            if order is None:
+                continue
+            order = canonical(order)
+            labels = np.empty(q.m, np.int32)
+            labels[order] = np.arange(q.m, dtype=np.int32)     # cell -> step (0-based)
+            data.append((uavq.mlp_features(q), labels, q.m))
+        del plan, out
+        if log:
+            log(f"labelled {min(c0 + chunk, len(grids))}/{len(grids)} ({ms / 1e3:.1f} s of annealing)")
     return data, ms
 
 
@@ -229,7 +237,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-n", type=int, default=2000)
     ap.add_argument("--heldout-n", type=int, default=200)
-    ap.add_argument("--label-replicas", type=int, default=256)
+    ap.add_argument("--label-replicas", type=int, default=4096)
     ap.add_argument("--label-sweeps", type=int, default=2000)
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
@@ -246,7 +254,7 @@ def main():
     log = lambda s: print(s, flush=True)
     T0, T1, seed = 200.0, 0.5, 1
     train_grids = make_instances(args.train_n, 10000)
-    data, label_ms = label_data(train_grids, args.label_replicas, args.label_sweeps, T0, T1, seed)
+    data, label_ms = label_data(train_grids, args.label_replicas, args.label_sweeps, T0, T1, seed, log=log)
     log(f"labelled {len(data)}/{len(train_grids)} training instances in {label_ms / 1e3:.1f} s")
     net, curve, train_s = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     ladder = [int(v) for v in args.ladder.split(",")]
