@@ -31,10 +31,6 @@ __device__ __forceinline__ uint4 philox(uint4 c, uint32_t k0, uint32_t k1) {
     return c;
 }
 
-__device__ __forceinline__ uint32_t pick4(uint4 v, int w) {
-    return w == 0 ? v.x : (w == 1 ? v.y : (w == 2 ? v.z : v.w));
-}
-
 __device__ __forceinline__ uint64_t ballot64(bool p) { return __ballot(p); }
 
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {

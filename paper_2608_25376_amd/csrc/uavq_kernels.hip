@@ -11,19 +11,29 @@
 // only the 2P R_t term; it changes Y_t (used by steps t-1 and t+1) by the
 // cost row of c*.
 //
-// Factored sweep, one replica per wavefront: the steps are visited in order;
+// Factored sweeps, one replica per wavefront: the steps are visited in order;
 // for step t every lane evaluates the sites of its own cells (c = lane + 64 j)
-// against the current state, a ballot finds the first accepted site c* in
-// site order, the flip is applied (O(m) update of Y_t) and evaluation resumes
-// at c* + 1.  Sites before c* were rejections under an unchanged state and
-// the random word of a site is addressed by (instance, replica, sweep, step,
-// cell) rather than consumed, so the result equals the sequential sweep bit
-// for bit.
+// against the state at the step start, and a ballot finds the first accepted
+// site c* in site order; the flip is applied and the walk resumes at c* + 1.
+// Sites before c* were rejections under an unchanged state, and the random
+// word of a site is addressed by (instance, replica, sweep, step, cell)
+// rather than consumed, so the result equals the sequential sweep bit for bit.
+// During the walk only R_t has changed for the remaining sites of step t, so
+// each open site's dE is its start value plus k (+-2P) for a uniform count k of
+// net 1s gained by the step; with the exact acceptance cut of each site's word
+// (the least d whose table entry is <= the word), a test is one compare.  The
+// dE each site was visited with is rebuilt at the step end (draw counts,
+// energy); Y_t takes the cost rows of the flipped cells.
 //
-// Replica state lives in registers: lane L holds the cell masks of steps
-// L + 1 + 64 j (bits = cells) and the occupation count of cells L + 64 j.  The
-// cost matrix D (bytes), the start-cell costs and a single row of the
-// acceptance table live in LDS and are shared by the block's replicas.
+// m <= 64 (k_sweep_ylds): lane c holds the column of cell c as a step mask,
+// the travel rows Y_t live in LDS per replica, and blocks of four steps are
+// first evaluated speculatively against the block-start state, which
+// finishes most blocks at low temperature without the walk.
+// m <= 192 (k_sweep_factored): lane L holds the cell masks of steps
+// L + 1 + 64 j (bits = cells) and the occupation count of cells L + 64 j, and
+// travel rows are rebuilt from the neighbouring steps' masks.
+// The cost matrix D, the start-cell costs and one row of the acceptance table
+// live in LDS and are shared by the block's replicas.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

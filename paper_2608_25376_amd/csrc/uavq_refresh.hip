@@ -34,12 +34,6 @@ __device__ __forceinline__ uint64_t spread8(uint32_t b) {
     return v;
 }
 
-__device__ __forceinline__ int64_t wsum64(int64_t v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // ------------------------------------------------------- energy refresh --
 // One wavefront per state.  LDS holds the cost matrix as two byte limbs
 // (row-major, rows padded to Kp = 32-multiple) and the start-cell costs.
@@ -128,7 +122,7 @@ __global__ __launch_bounds__(256) void k_energy_refresh(EnergyArgs a) {
         for (int w = 0; w < W; w++) R += __popc(x[t * W + w]);
         rest += (int64_t)a.P * R * (R - 1) - 2LL * a.P * R;
     }
-    const int64_t tot = wsum64(travel + rest);
+    const int64_t tot = wave_sum64(travel + rest);
     if (lane == 0) a.E[st] = a.c0 + tot;
 }
 
@@ -263,7 +257,7 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
             }
         }
         // E = c0 + (1/2) sum_k x_k (h_k + b_k)
-        E = d.c0 + wsum64(part) / 2;
+        E = d.c0 + wave_sum64(part) / 2;
         uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
         for (int i = L; i < d.state_words; i += 64) bs[i] = st[i];
     }

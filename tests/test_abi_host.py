@@ -146,3 +146,23 @@ def test_features_match_oracle(U, oracle_lib):
         assert X.shape == (q.m, 16)
         assert np.abs(X - Xo).max() <= 1e-7
     assert U.mlp_param_count() == mlp.N_PARAMS
+
+
+def test_plan_kernel_name_without_device(U):
+    q = U.qubo_build(3, 3, dense=True)
+    p = U.Plan([q], [0], 4, 10, 10.0, 1.0)
+    with pytest.raises(U.UavqError):
+        p.kernel_name(0)                          # classes are 1..3
+    with pytest.raises(U.UavqError):
+        p.kernel_name(4)
+    assert p.kernel_name(2) == ""                 # no instance with 64 < m <= 128
+    pd = U.Plan([q], [0], 4, 10, 10.0, 1.0, dense=True)
+    assert pd.kernel_name(1) == "k_sweep_dense"
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if not has_gpu:
+        with pytest.raises(U.UavqError):          # the launch shape needs the device's CU count
+            p.kernel_name(1)
