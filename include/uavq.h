@@ -226,6 +226,23 @@ typedef struct {              /* device outputs, caller-owned; NULL = not wanted
 int uavq_anneal_batch(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
                       const uavq_anneal_out *out, void *stream);
 
+/* anneal_segment -- the same annealing cut into pieces: runs sweeps
+ * s_begin .. s_end-1 (0 <= s_begin <= s_end <= S) of the plan's S-sweep
+ * schedule.  With resume = 0 the replicas start as in anneal_batch (initial
+ * states from init, best_E = +inf).  With resume != 0 they continue from what
+ * *out holds: final_states is the working state, and best_E, best_sweep,
+ * best_states, accepts and draws are carried on, so a run cut into
+ * [0, S1) + [S1, S) -- or checkpointed after S1 (copy final_states, best_E,
+ * best_sweep, best_states, accepts and draws out), restored into the buffers and resumed -- gives bit for bit the
+ * outputs of one anneal_batch call (every random draw is keyed by its sweep,
+ * so the split leaves the random streams unchanged).  init->states and
+ * init->seeded are ignored on resume; init->start_sweep still applies.  The
+ * per-instance outputs and check_E describe the state after s_end.
+ * anneal_batch is anneal_segment(0, S, resume = 0).  Errors: UAVQ_EINVAL for
+ * a range outside [0, S] or any argument anneal_batch rejects. */
+int uavq_anneal_segment(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
+                        const uavq_anneal_out *out, int32_t s_begin, int32_t s_end, int32_t resume, void *stream);
+
 /* Autotuner: times anneal_batch launch shapes (replicas per workgroup per
  * chunk class, m <= 64 kernel variant) on a short trial of trial_sweeps
  * sweeps of these instances, with device memory it allocates and frees

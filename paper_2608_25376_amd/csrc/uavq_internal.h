@@ -51,6 +51,8 @@ struct KArgs {
     int32_t thr_stride;         // multiple of 4
     const int32_t *dcut;        // S: least d with thr[s][d] == 0
     int32_t S, Dmax;
+    int32_t s_begin, s_end;     // this launch runs sweeps s_begin .. s_end-1 of the S-sweep schedule
+    int32_t resume;             // continue from the outputs of a segment that ended at s_begin
     float tl2_a, tl2_b;         // T_s ln 2 ~= exp2(tl2_a + tl2_b s): starting guess for acceptance cuts
     uint32_t seed;
     int32_t n_inst;

@@ -53,6 +53,7 @@ namespace uavq {
 // One block per work item; every unit (replica, 4-step block tb, word w)
 // draws the 32 cells of that word for steps 4 tb + 1 .. 4 tb + 4 (stream 1).
 __global__ __launch_bounds__(256) void k_init_states(KArgs a) {
+    if (a.resume) return;   // the working states continue a previous segment
     const WorkItem it = a.items[blockIdx.x];
     const InstDesc d = a.desc[it.inst];
     const int m = d.m, W = d.row_words, nb = (m + 3) >> 2;
@@ -221,13 +222,13 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     const bool active = wave < it.nrep;
     const int r = it.rep0 + wave;
     const int64_t grep = d.rep_base + r;
-    const int s0 = active ? (a.start_sweep ? a.start_sweep[grep] : 0) : a.S;
-    if (threadIdx.x == 0) s_first_sh = a.S;
+    const int s0 = active ? max(a.start_sweep ? a.start_sweep[grep] : 0, a.s_begin) : a.s_end;
+    if (threadIdx.x == 0) s_first_sh = a.s_end;
     __syncthreads();
     if (L == 0) atomicMin(&s_first_sh, s0);
     __syncthreads();
     const int s_first = s_first_sh;
-    if (s_first < a.S) {
+    if (s_first < a.s_end) {
         const int n4 = (a.dcut[s_first] + 2 + 3) >> 2;   // through index dcut + 1
         const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
         uint4 *dst = reinterpret_cast<uint4 *>(sthr);
@@ -247,7 +248,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         Cc[j] = 0;
     }
     // the best state starts as the initial state (kept if no sweep improves on +inf)
-    if (active) {
+    if (active && !a.resume) {
         uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
 #pragma unroll
         for (int j = 0; j < NJ; j++) {
@@ -291,9 +292,14 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         E = d.c0 + rowterm + wave_sum64(lane_e);
     }
 
+    // best so far and counters: fresh, or those of the previous segment
     int64_t bestE = LLONG_MAX;
     int bestS = -1;
-    uint64_t nacc = 0, ndraw = 0;
+    uint64_t nacc = 0, ndraw = 0;   // this launch's counts (a resumed run adds the stored ones at the end)
+    if (active && a.resume) {
+        bestE = a.best_E[grep];
+        bestS = a.best_sweep[grep];
+    }
     int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
     uint32_t ndraw_lane = 0;   // draws of the lane's sites
     int dep[NJ];   // start-cell costs of this lane's cells (the fixed rows 0 and m+1)
@@ -303,10 +309,10 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         dep[j] = c < m ? sdep[c] : 0;
     }
 
-    for (int s = s_first; s < a.S; s++) {
+    for (int s = s_first; s < a.s_end; s++) {
         // next table row: loads issued now, stored to LDS after this sweep
         uint4 pre[KP];
-        const bool has_next = s + 1 < a.S;
+        const bool has_next = s + 1 < a.s_end;
         const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 2 + 3) >> 2 : 0;
         const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
 #pragma unroll
@@ -543,6 +549,10 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         }
         ndraw += (uint64_t)wave_sum64((int64_t)ndraw_lane);
         if (L == 0) {
+            if (a.resume) {
+                nacc += a.accepts[grep];
+                ndraw += a.draws[grep];
+            }
             a.final_E[grep] = E;
             a.best_E[grep] = bestE;
             a.best_sweep[grep] = bestS;
@@ -618,13 +628,13 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     const bool active = wave < it.nrep;
     const int r = it.rep0 + wave;
     const int64_t grep = d.rep_base + r;
-    const int s0 = active ? (a.start_sweep ? a.start_sweep[grep] : 0) : a.S;
-    if (threadIdx.x == 0) s_first_sh = a.S;
+    const int s0 = active ? max(a.start_sweep ? a.start_sweep[grep] : 0, a.s_begin) : a.s_end;
+    if (threadIdx.x == 0) s_first_sh = a.s_end;
     __syncthreads();
     if (L == 0) atomicMin(&s_first_sh, s0);
     __syncthreads();
     const int s_first = s_first_sh;
-    if (s_first < a.S) {
+    if (s_first < a.s_end) {
         const int n4 = (uniform_load(a.dcut, s_first) + 2 + 3) >> 2;   // through index dcut + 1
         const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
         uint4 *dst = reinterpret_cast<uint4 *>(sthr);
@@ -646,9 +656,11 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         if (lane_in) {
             rw0 = st[L * W];
             if (W > 1) rw1 = st[L * W + 1];
-            uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
-            bs[L * W] = rw0;
-            if (W > 1) bs[L * W + 1] = rw1;
+            if (!a.resume) {   // the best state starts as the initial state
+                uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
+                bs[L * W] = rw0;
+                if (W > 1) bs[L * W + 1] = rw1;
+            }
         }
         int64_t lane_e = 0, rowterm = 0;
         int Yp = dep;
@@ -680,17 +692,23 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         for (int t = m + 1; t <= m + 8; t++) Yw[(t - 1) * 64 + L] = (uint16_t)(t == m + 1 && d.closed ? dep : 0);
     }
 
+    // best so far and counters: fresh, or those of the previous segment
     int64_t bestE = LLONG_MAX;
     int bestS = -1;
     uint64_t bestcm = cm;
+    bool improved = false;      // the best state changed in this launch
     int Kc = twoP * (Cc - 1);   // 2P (C_c - 1): the cell-count part of the field
-    uint64_t nacc = 0, ndraw = 0;
+    uint64_t nacc = 0, ndraw = 0;   // this launch's counts (a resumed run adds the stored ones at the end)
+    if (active && a.resume) {
+        bestE = a.best_E[grep];
+        bestS = a.best_sweep[grep];
+    }
     int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
     uint32_t ndraw_lane = 0;   // draws of the lane's sites visited by the sequential walk
 
-    for (int s = s_first; s < a.S; s++) {
+    for (int s = s_first; s < a.s_end; s++) {
         uint4 pre[KP];
-        const bool has_next = s + 1 < a.S;
+        const bool has_next = s + 1 < a.s_end;
         const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 2 + 3) >> 2 : 0;
         const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
 #pragma unroll
@@ -873,6 +891,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 bestE = E;
                 bestS = s;
                 bestcm = cm;
+                improved = true;
             }
         }
         // one table row in LDS: every wave is done with row s before row s + 1
@@ -906,7 +925,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         if (lane_in) {
             st[L * W] = f0;
             if (W > 1) st[L * W + 1] = f1;
-            if (bestS >= 0) {
+            if (improved) {
                 uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
                 bs[L * W] = b0;
                 if (W > 1) bs[L * W + 1] = b1;
@@ -914,6 +933,10 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         }
         ndraw += (uint64_t)wave_sum64(lane_in ? (int64_t)ndraw_lane : 0);
         if (L == 0) {
+            if (a.resume) {
+                nacc += a.accepts[grep];
+                ndraw += a.draws[grep];
+            }
             a.final_E[grep] = E;
             a.best_E[grep] = bestE;
             a.best_sweep[grep] = bestS;
@@ -1183,7 +1206,15 @@ const char *uavq_plan_kernel_name(const uavq_plan *pl, int32_t cls) {
 
 int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
                       const uavq_anneal_out *out, void *stream) {
+    if (!pl) return set_error(UAVQ_EINVAL, "anneal_batch: null argument");
+    return uavq_anneal_segment(pl, d_ws, ws_bytes, init, out, 0, pl->S, 0, stream);
+}
+
+int uavq_anneal_segment(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
+                        const uavq_anneal_out *out, int32_t s_begin, int32_t s_end, int32_t resume, void *stream) {
     if (!pl || !out) return set_error(UAVQ_EINVAL, "anneal_batch: null argument");
+    if (s_begin < 0 || s_end < s_begin || s_end > pl->S)
+        return set_error(UAVQ_EINVAL, "anneal_segment: sweep range [%d, %d) outside [0, %d]", s_begin, s_end, pl->S);
     if (pl->total_rep == 0) return UAVQ_OK;
     if (!d_ws || ws_bytes < pl->ws_bytes) return set_error(UAVQ_EINVAL, "anneal_batch: workspace too small");
     if (!out->final_states || !out->final_E || !out->best_E || !out->best_sweep || !out->best_states ||
@@ -1203,6 +1234,9 @@ int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const ua
     a.thr = (const uint32_t *)(ws + pl->thr_off);
     a.dcut = (const int32_t *)(ws + pl->dcut_off);
     a.S = pl->S;
+    a.s_begin = s_begin;
+    a.s_end = s_end;
+    a.resume = resume ? 1 : 0;
     a.Dmax = pl->Dmax;
     a.thr_stride = pl->thr_stride;
     a.tl2_a = (float)std::log2((double)pl->p.T0 * 0.69314718055994531);
@@ -1237,6 +1271,7 @@ int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const ua
                           out->best_E, out->best_sweep, out->best_states, out->accepts, out->draws, out->inst_best_E,
                           out->inst_best_replica, out->inst_best_sweep, out->inst_best_state, out->check_E};
     for (const void *p : ptrs) key = mix64(key, (uint64_t)(uintptr_t)p);
+    key = mix64(mix64(mix64(key, (uint64_t)s_begin), (uint64_t)s_end), (uint64_t)a.resume);
     hipStream_t st = (hipStream_t)stream;
     if (!mp->graph_exec || mp->graph_key != key) {
         release_graph(mp);

@@ -228,13 +228,13 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
     const int r = blockIdx.x * nw + wave;
     const bool active = r < d.nrep;
     const int64_t grep = d.rep_base + r;
-    const int s0 = active ? (a.start_sweep ? a.start_sweep[grep] : 0) : a.S;
-    if (threadIdx.x == 0) s_first_sh = a.S;
+    const int s0 = active ? max(a.start_sweep ? a.start_sweep[grep] : 0, a.s_begin) : a.s_end;
+    if (threadIdx.x == 0) s_first_sh = a.s_end;
     __syncthreads();
     if (L == 0) atomicMin(&s_first_sh, s0);
     __syncthreads();
     const int s_first = s_first_sh;
-    if (s_first < a.S) {
+    if (s_first < a.s_end) {
         const int n = a.dcut[s_first];
         for (int i = threadIdx.x; i < n; i += nthr) sthr[(s_first & 1) * Ts + i] = a.thr[(size_t)s_first * Ts + i];
     }
@@ -258,15 +258,25 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
         }
         // E = c0 + (1/2) sum_k x_k (h_k + b_k)
         E = d.c0 + wave_sum64(part) / 2;
-        uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
-        for (int i = L; i < d.state_words; i += 64) bs[i] = st[i];
+        if (!a.resume) {   // the best state starts as the initial state
+            uint32_t *bs = a.best_states + d.state_off + (int64_t)r * d.state_words;
+            for (int i = L; i < d.state_words; i += 64) bs[i] = st[i];
+        }
     }
     __syncthreads();
 
+    // best so far and counters: fresh, or those of the previous segment
     int64_t bestE = LLONG_MAX;
     int bestS = -1;
+    bool improved = false;   // the best state changed in this launch
     uint64_t bestxb = xb, nacc = 0, ndraw = 0;
-    for (int s = s_first; s < a.S; s++) {
+    if (active && a.resume) {
+        bestE = a.best_E[grep];
+        bestS = a.best_sweep[grep];
+        nacc = a.accepts[grep];
+        ndraw = a.draws[grep];
+    }
+    for (int s = s_first; s < a.s_end; s++) {
         const uint32_t *thr = sthr + (s & 1) * Ts;
         const int dcut = a.dcut[s];
         if (active && s >= s0) {
@@ -320,9 +330,10 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
                 bestE = E;
                 bestS = s;
                 bestxb = xb;
+                improved = true;
             }
         }
-        if (s + 1 < a.S) {
+        if (s + 1 < a.s_end) {
             const int n = a.dcut[s + 1];
             uint32_t *dst = sthr + ((s + 1) & 1) * Ts;
             const uint32_t *src = a.thr + (size_t)(s + 1) * Ts;
@@ -346,7 +357,7 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
             }
             if (L == 0) {
                 st[w] = fw;
-                if (bestS >= 0) bs[w] = bw;
+                if (improved) bs[w] = bw;
             }
         }
         if (L == 0) {

@@ -7,6 +7,7 @@ device memory and streams, nothing else).  The library must have been built
 """
 import ctypes as C
 import os
+import time
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -79,7 +80,7 @@ EXPORTS = [
     "uavq_energy_workspace_bytes", "uavq_energy_eval_dev", "uavq_decode_path", "uavq_schedule",
     "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_kernel_name", "uavq_plan_layout",
     "uavq_plan_upload",
-    "uavq_anneal_batch", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
+    "uavq_anneal_batch", "uavq_anneal_segment", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
     "uavq_mlp_param_count", "uavq_mlp_features", "uavq_mlp_workspace_bytes", "uavq_mlp_forward",
     "uavq_mlp_loss_grad", "uavq_mlp_adam", "uavq_quantize_marginals", "uavq_sample_seeds",
 ]
@@ -119,6 +120,7 @@ def lib():
         L.uavq_plan_layout.argtypes = [vp, P(C.c_int64), P(C.c_int64)]
         L.uavq_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
         L.uavq_anneal_batch.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), vp]
+        L.uavq_anneal_segment.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), C.c_int32, C.c_int32, C.c_int32, vp]
         L.uavq_plan_set_timing.argtypes = [vp, C.c_int32]
         L.uavq_plan_sweep_ms.argtypes = [vp, P(C.c_float)]
         L.uavq_autotune.argtypes = [P(vp), C.c_int32, P(C.c_uint32), P(_Params), C.c_int32, C.c_char_p, P(Tune)]
@@ -287,6 +289,18 @@ class AnnealResult:
     inst_best_state: object
 
 
+# outputs that carry a replica across a segment boundary (what a checkpoint holds)
+CHECKPOINT_FIELDS = ("final_states", "best_E", "best_sweep", "best_states", "accepts", "draws")
+
+
+def _sync(stream):
+    import torch
+    if stream is None:
+        torch.cuda.synchronize()
+    else:
+        stream.synchronize()
+
+
 class Plan:
     """uavq_plan_create + workspace; call ``upload`` once, then ``anneal``."""
 
@@ -359,17 +373,68 @@ class Plan:
             inst_best_state=z(inst_words, torch.int32))
 
     def anneal(self, out: Optional[AnnealResult] = None, init_states=None, seeded=None, start_sweep=None,
-               check_E=None, stream=None) -> AnnealResult:
-        """anneal_batch on this plan's workspace (asynchronous on ``stream``)."""
+               check_E=None, stream=None, s_begin: int = 0, s_end: Optional[int] = None,
+               resume: bool = False) -> AnnealResult:
+        """anneal_batch on this plan's workspace (asynchronous on ``stream``).  With a sweep range
+        (anneal_segment) only sweeps s_begin .. s_end-1 of the schedule run; ``resume`` continues
+        from what ``out`` holds (the outputs of a segment that ended at s_begin, or a restored
+        checkpoint)."""
         if self.ws is None:
             raise RuntimeError("Plan.upload() must precede anneal()")
         if out is None:
+            if resume:
+                raise ValueError("resume needs the outputs of the previous segment")
             out = self.alloc_outputs(self.ws.device)
         init = _Init(_dptr(init_states), _dptr(seeded), _dptr(start_sweep))
         o = _Out(*[_dptr(getattr(out, f)) if f != "check_E" else _dptr(check_E) for f, _ in _Out._fields_])
-        _check(lib().uavq_anneal_batch(self._h, _dptr(self.ws), self.ws_bytes, C.byref(init), C.byref(o),
-                                       _stream_handle(stream)))
+        if s_begin == 0 and s_end is None and not resume:
+            _check(lib().uavq_anneal_batch(self._h, _dptr(self.ws), self.ws_bytes, C.byref(init), C.byref(o),
+                                           _stream_handle(stream)))
+        else:
+            _check(lib().uavq_anneal_segment(self._h, _dptr(self.ws), self.ws_bytes, C.byref(init), C.byref(o),
+                                             int(s_begin), int(self.sweeps if s_end is None else s_end),
+                                             1 if resume else 0, _stream_handle(stream)))
         return out
+
+    def checkpoint(self, out: AnnealResult) -> dict:
+        """Copy of everything a resumed segment reads (device tensors, on the stream's device)."""
+        return {f: getattr(out, f).clone() for f in CHECKPOINT_FIELDS}
+
+    def restore(self, ckpt: dict, out: Optional[AnnealResult] = None) -> AnnealResult:
+        """Write a checkpoint into output buffers (fresh ones if ``out`` is None); then resume with
+        ``anneal(out=out, s_begin=<sweeps done>, resume=True)``."""
+        if out is None:
+            out = self.alloc_outputs(self.ws.device)
+        for f in CHECKPOINT_FIELDS:
+            getattr(out, f).copy_(ckpt[f])
+        return out
+
+    def anneal_time_limited(self, budget_ms: float, segment_sweeps: Optional[int] = None,
+                            out: Optional[AnnealResult] = None, init_states=None, seeded=None, start_sweep=None,
+                            stream=None):
+        """Time-limit mode: run the schedule in segments of ``segment_sweeps`` sweeps and stop at
+        the first segment boundary after which the next segment would overrun ``budget_ms`` of wall
+        time (predicted from the time per sweep so far).  The first segment always runs.  Returns
+        (outputs, sweeps completed); the outputs equal those of ``anneal(s_end=<sweeps completed>)``
+        bit for bit, so only the stopping point depends on timing."""
+        S = self.sweeps
+        seg = int(segment_sweeps) if segment_sweeps else max(1, S // 20)
+        if seg < 1:
+            raise ValueError("segment_sweeps must be positive")
+        t0 = time.perf_counter()
+        done = min(seg, S)
+        out = self.anneal(out=out, init_states=init_states, seeded=seeded, start_sweep=start_sweep,
+                          stream=stream, s_begin=0, s_end=done)
+        _sync(stream)
+        while done < S:
+            spent = (time.perf_counter() - t0) * 1e3
+            nxt = min(done + seg, S)
+            if spent + spent / done * (nxt - done) > budget_ms:
+                break
+            self.anneal(out=out, start_sweep=start_sweep, stream=stream, s_begin=done, s_end=nxt, resume=True)
+            _sync(stream)
+            done = nxt
+        return out, done
 
 
 def anneal_batch(plan: Plan, **kw) -> AnnealResult:

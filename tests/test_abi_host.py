@@ -166,3 +166,20 @@ def test_plan_kernel_name_without_device(U):
     if not has_gpu:
         with pytest.raises(U.UavqError):          # the launch shape needs the device's CU count
             p.kernel_name(1)
+
+
+def test_segment_range_validation(U):
+    """anneal_segment rejects a sweep range outside [0, S] before touching the
+    device (so this runs without a GPU)."""
+    import ctypes as C
+    q = U.qubo_build(3, 3)
+    p = U.Plan([q], [0], 4, 10, 10.0, 1.0)
+    init, out = U._Init(), U._Out()
+    for b, e in [(-1, 5), (6, 5), (0, 11), (11, 11)]:
+        rc = U.lib().uavq_anneal_segment(p._h, None, 0, C.byref(init), C.byref(out), b, e, 0, None)
+        assert rc == U.EINVAL, (b, e)
+        assert b"sweep range" in U.lib().uavq_last_error()
+    # a valid range still needs a workspace and the outputs
+    rc = U.lib().uavq_anneal_segment(p._h, None, 0, C.byref(init), C.byref(out), 0, 10, 1, None)
+    assert rc == U.EINVAL
+    assert U.lib().uavq_anneal_segment(None, None, 0, None, None, 0, 1, 0, None) == U.EINVAL
