@@ -141,11 +141,13 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
 #define UAVQ_GRAPH 0x40u           /* capture the launch sequence of anneal_batch into a HIP graph
                                       on first use and replay it while the buffers and stream are
                                       the same; needs a non-default stream */
+#define UAVQ_VARIANT_NOPRODUCER 0x80u /* m <= 64 at one wave per SIMD: no cut-producing wave beside
+                                      each replica's wave (a schedule choice; same results) */
 
 /* Launch shape chosen by uavq_autotune (never changes results). */
 typedef struct {
     int32_t waves_per_block[4];  /* per chunk class c = ceil(m/64) (index 0 unused); 0 = default */
-    uint32_t variant_flags;      /* 0 or UAVQ_VARIANT_ROWMASK */
+    uint32_t variant_flags;      /* 0, UAVQ_VARIANT_ROWMASK and/or UAVQ_VARIANT_NOPRODUCER */
     float trial_ms;              /* measured time of the chosen shape (trial run) */
 } uavq_tune;
 

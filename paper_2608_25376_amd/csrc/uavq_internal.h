@@ -112,6 +112,8 @@ struct uavq_plan {
     int32_t max_blocks[uavq::kMaxChunks + 2] = {};   // resident blocks per CU of each class's kernel
     size_t lds_class[uavq::kMaxChunks + 2] = {};
     int32_t ylds_w1 = 0;         // the m <= 64 sweep runs at one wave per SIMD (launch fits the chip)
+    int32_t ylds_pc = 0;         // ... with a cut-producing wave beside each replica's wave
+    int32_t no_producer = 0;     // UAVQ_VARIANT_NOPRODUCER
     size_t queue_off = 0;                 // workspace: item counters (persistent mode)
     void *graph_exec = nullptr;           // cached hipGraphExec_t (graph mode)
     uint64_t graph_key = 0;

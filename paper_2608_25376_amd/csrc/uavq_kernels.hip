@@ -142,6 +142,17 @@ __device__ __forceinline__ void accept_cuts(const uint4 &u4, float tl2, float e0
     cut3 = cut[3];
 }
 
+// Philox words of one lane's block of four steps and their exact cuts, packed
+// as four uint16 (the m <= 64 producer/consumer sweep's fallback when no
+// producer made them; out of line, as it is rarely taken).
+__device__ __attribute__((noinline)) uint2 draw_cuts(uint32_t cbase, uint32_t s, uint32_t r, uint32_t inst, uint32_t seed,
+                                                     float tl2, float e0, float dm1, int dcut, const uint32_t *thr) {
+    const uint4 u4 = philox(make_uint4(cbase, s, r, inst), seed, 0u);
+    int c0, c1, c2, c3;
+    accept_cuts(u4, tl2, e0, dm1, dcut, thr, c0, c1, c2, c3);
+    return make_uint2((uint32_t)c0 | ((uint32_t)c1 << 16), (uint32_t)c2 | ((uint32_t)c3 << 16));
+}
+
 template <int NJ>
 struct RowOps {
     // mask of the step held by lane lt of one chunk of the step masks
@@ -591,6 +602,18 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
 // kept in LDS (int16, one 64-entry row per step) and updated on accepts, so
 // that visiting a step costs one LDS read (issued a step ahead) and a ballot.
 // Same trajectory as k_sweep_factored bit for bit.
+//
+// PC (producer/consumer): the block holds two waves per replica.  The random
+// words, and so the acceptance cuts, depend only on (site, sweep, replica),
+// not on the state, so the second wave (the producer) computes the cuts of
+// every site for sweep s+1 (Philox + the exact cut search against table row
+// s+1) while the first (the consumer) sweeps s with the cuts it was given, at
+// no cost beyond one LDS read per block; the two share a SIMD, so the
+// producer's vector work fills the issue slots the consumer's latency-bound
+// walk leaves idle.  The producer works for sweep s+1 only if sweep s-1 had a
+// draw; without cuts the consumer draws for itself, reading the table row from
+// global memory (the LDS row is the producer's).
+template <bool PC>
 __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem) {
     constexpr int KP = 6;
     const WorkItem it = a.items[itx];
@@ -598,6 +621,10 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     const int m = d.m, W = d.row_words, twoP = 2 * d.P;
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
     const int nthr = blockDim.x, nwaves = nthr >> 6;
+    const int ncons = PC ? nwaves >> 1 : nwaves;    // replica slots (consumer waves)
+    const bool producer = PC && wave >= ncons;
+    const int slot = producer ? wave - ncons : wave;
+    const int NB = (m + 3) >> 2;                    // blocks of four steps
     const int Ts = a.thr_stride;
 
     // LDS: the table row | D | start-cell costs | signed cost rows | per-wave travel rows
@@ -608,9 +635,14 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     // change of Y_t when step t gains or loses cell c
     int16_t *sDs = reinterpret_cast<int16_t *>(sdep + al16((size_t)m));
     uint16_t *Yall = reinterpret_cast<uint16_t *>(sDs + 2 * 64 * (size_t)m);
-    uint16_t *Yw = Yall + (size_t)wave * 64 * (m + 8);   // Y_t[c] at Yw[(t-1)*64 + c], t = 1..m+8
+    uint16_t *Yw = Yall + (size_t)slot * 64 * (m + 8);   // Y_t[c] at Yw[(t-1)*64 + c], t = 1..m+8
+    // PC: per slot, cuts of two sweeps (by parity) [2][NB][64] as four uint16
+    // per lane and block, then per slot and parity the flags "cuts valid" and
+    // "the sweep had a draw"
+    uint2 *cutbuf = reinterpret_cast<uint2 *>(smem + al16(reinterpret_cast<uint8_t *>(Yall + (size_t)ncons * 64 * (m + 8)) - smem));
+    int *pc_valid = reinterpret_cast<int *>(cutbuf + (size_t)ncons * 2 * NB * 64);
+    int *pc_drew = pc_valid + 2 * ncons;
     __shared__ int s_first_sh;
-    (void)nwaves;
 
     {
         const uint4 *gD = reinterpret_cast<const uint4 *>(a.ws + d.d_off);
@@ -625,18 +657,24 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             sDs[i] = (int16_t)(i < 64 * m ? v : -v);
         }
     }
-    const bool active = wave < it.nrep;
-    const int r = it.rep0 + wave;
+    const bool active = slot < it.nrep;
+    const int r = it.rep0 + slot;
     const int64_t grep = d.rep_base + r;
     const int s0 = active ? max(a.start_sweep ? a.start_sweep[grep] : 0, a.s_begin) : a.s_end;
     if (threadIdx.x == 0) s_first_sh = a.s_end;
+    if (PC && producer && L < 2) {
+        pc_valid[2 * slot + L] = 0;   // no cuts yet
+        pc_drew[2 * slot + L] = 1;    // no history: produce
+    }
     __syncthreads();
     if (L == 0) atomicMin(&s_first_sh, s0);
     __syncthreads();
     const int s_first = s_first_sh;
-    if (s_first < a.s_end) {
-        const int n4 = (uniform_load(a.dcut, s_first) + 2 + 3) >> 2;   // through index dcut + 1
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
+    // the LDS table row: row s (row s+1, the producer's, with PC)
+    const int s_row0 = PC ? s_first + 1 : s_first;
+    if (s_row0 < a.s_end) {
+        const int n4 = (uniform_load(a.dcut, s_row0) + 2 + 3) >> 2;   // through index dcut + 1
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_row0 * Ts);
         uint4 *dst = reinterpret_cast<uint4 *>(sthr);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
     }
@@ -651,7 +689,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     uint64_t cm = 0;      // bit t-1: x_{t, L}
     int Cc = 0;
     int64_t E = 0;
-    if (active) {
+    if (active && !producer) {
         uint32_t rw0 = 0u, rw1 = 0u;
         if (lane_in) {
             rw0 = st[L * W];
@@ -708,19 +746,44 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
 
     for (int s = s_first; s < a.s_end; s++) {
         uint4 pre[KP];
-        const bool has_next = s + 1 < a.s_end;
-        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 2 + 3) >> 2 : 0;
-        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
+        const int s_pre = PC ? s + 2 : s + 1;   // the row the LDS table holds next
+        const bool has_next = s_pre < a.s_end;
+        const int n4_next = has_next ? (uniform_load(a.dcut, s_pre) + 2 + 3) >> 2 : 0;
+        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_pre * Ts);
 #pragma unroll
         for (int k = 0; k < KP; k++) {
             const int i = threadIdx.x + k * nthr;
             pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
         }
-        const uint32_t *thr = sthr;
+        // with PC the consumer's own draws read row s from global memory
+        const uint32_t *thr = PC ? a.thr + (size_t)s * Ts : sthr;
         const int dcut = uniform_load(a.dcut, s);
         const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
-        if (active && s >= s0) {
+        if (PC && producer) {
+            // cuts of every site for sweep s+1 (table row s+1 is in LDS)
+            const int sp = s + 1;
+            const bool prod = active && sp < a.s_end && sp >= s0 && pc_drew[2 * slot + ((s - 1) & 1)] != 0;
+            if (L == 0) pc_valid[2 * slot + (sp & 1)] = prod ? 1 : 0;
+            if (prod) {
+                const int dcut_p = uniform_load(a.dcut, sp);
+                const float tl2p = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)sp);
+                const float e0p = 32.0f * tl2p - 0.5f, dm1p = (float)(dcut_p - 1);
+                uint2 *cb = cutbuf + (size_t)(2 * slot + (sp & 1)) * NB * 64 + L;
+                for (int b = 0; b < NB; b++) {
+                    const uint4 u4 = philox(make_uint4((uint32_t)L + 65536u * (uint32_t)b, (uint32_t)sp, (uint32_t)r,
+                                                       d.inst_id), a.seed, 0u);
+                    int c0, c1, c2, c3;
+                    accept_cuts(u4, tl2p, e0p, dm1p, dcut_p, sthr, c0, c1, c2, c3);
+                    cb[b * 64] = make_uint2((uint32_t)c0 | ((uint32_t)c1 << 16), (uint32_t)c2 | ((uint32_t)c3 << 16));
+                }
+            }
+        } else if (active && s >= s0) {
+            // PC: cuts for this sweep from the producer, if it made them
+            const bool cv = PC && pc_valid[2 * slot + (s & 1)] != 0;
+            const uint2 *cbs = cutbuf + (size_t)(2 * slot + (s & 1)) * NB * 64 + L;
+            uint2 cwn = PC ? cbs[0] : make_uint2(0u, 0u);   // the next block's cuts, read a block ahead
+            const uint32_t ndl0 = ndraw_lane;
             // Steps are visited in blocks of four (the Philox blocks); Yv[k] holds
             // Y_{t0-1+k} for the block starting at step t0, and the travel rows of
             // the next block are prefetched from LDS while this one is processed.
@@ -739,6 +802,18 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 for (int k = 0; k < 4; k++) Yv[2 + k] = pf[k];
 #pragma unroll
                 for (int k = 0; k < 4; k++) pf[k] = Yw[(t0 + 4 + k) * 64 + L];   // steps t0+5.. (padded)
+                // the producer's cuts of this block's four steps (PC)
+                uint2 cw = cwn;
+                if (PC) cwn = cbs[min(((t0 - 1) >> 2) + 1, NB - 1) * 64];
+                bool have_ct = cv;
+                // without the producer's cuts, draw them here (kept out of line: rare)
+                auto need_cuts = [&]() {
+                    if (!have_ct) {
+                        cw = draw_cuts((uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2), (uint32_t)s, (uint32_t)r,
+                                       d.inst_id, a.seed, tl2, e0, dm1, dcut, thr);
+                        have_ct = true;
+                    }
+                };
                 bool have_u = false;
                 uint4 u4 = make_uint4(0u, 0u, 0u, 0u);
                 // Speculative pass: every step of the block evaluated against the
@@ -769,6 +844,20 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                     const int mn = min(min(dEs[0], dEs[1]), min(dEs[2], dEs[3]));
                     if (!(ballot64(mn < dcut) & lanes_m)) {
                         done = true;                 // nothing below the cut: all rejected, no draw
+                    } else if (PC) {
+                        // exact cuts at hand: the block is finished if no site is below its cut
+                        // (then every dE >= cut >= 1, and those below dcut drew)
+                        need_cuts();
+                        const int ct0 = (int)(cw.x & 0xffffu), ct1 = (int)(cw.x >> 16);
+                        const int ct2 = (int)(cw.y & 0xffffu), ct3 = (int)(cw.y >> 16);
+                        const bool acc = lane_in & ((dEs[0] < ct0) | (dEs[1] < ct1) | (dEs[2] < ct2) | (dEs[3] < ct3));
+                        if (!ballot64(acc)) {
+                            done = true;
+                            const bool n0 = lane_in && dEs[0] < dcut, n1 = lane_in && dEs[1] < dcut;
+                            const bool n2 = lane_in && dEs[2] < dcut, n3 = lane_in && dEs[3] < dcut;
+                            ndraw_s += (uint32_t)(__popcll(ballot64(n0)) + __popcll(ballot64(n1)) +
+                                                  __popcll(ballot64(n2)) + __popcll(ballot64(n3)));
+                        }
                     } else if (!(ballot64(mn <= 0) & lanes_m)) {
                         // only draws: take them all; the block is finished if none accepts
                         uint32_t cbase = (uint32_t)L + 65536u * (uint32_t)((t0 - 1) >> 2);
@@ -794,8 +883,15 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                     // Sequential walk.  Until a site of the block needs a draw the
                     // cut is 1 (accept iff dE <= 0); from then on the exact cuts of
                     // the block's four steps make every acceptance test one compare.
-                    bool have_cut = false;
+                    bool have_cut = PC;   // PC: always the exact cuts
                     int cut0 = 1, cut1 = 1, cut2 = 1, cut3 = 1;
+                    if (PC) {
+                        need_cuts();
+                        cut0 = (int)(cw.x & 0xffffu);
+                        cut1 = (int)(cw.x >> 16);
+                        cut2 = (int)(cw.y & 0xffffu);
+                        cut3 = (int)(cw.y >> 16);
+                    }
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
                         const int t = t0 + i;
@@ -883,6 +979,11 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             }
             nacc += nacc_s;
             ndraw += ndraw_s;
+            if (PC) {
+                // tell the producer whether this sweep drew (it then makes the cuts of sweep s+2)
+                const bool drew = ndraw_s != 0 || (ballot64(ndraw_lane != ndl0) & lanes_m) != 0;
+                if (L == 0) pc_drew[2 * slot + (s & 1)] = drew ? 1 : 0;
+            }
             if (nacc_s) {
                 E += wave_sum64((int64_t)Elane);
                 Elane = 0;
@@ -909,7 +1010,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         __syncthreads();
     }
 
-    if (active) {
+    if (active && !producer) {
         // columns -> rows for the final and best states
         uint32_t f0 = 0u, f1 = 0u, b0 = 0u, b1 = 0u;
         for (int t = 1; t <= m; t++) {
@@ -951,7 +1052,7 @@ __global__ __launch_bounds__(1024) void k_sweep_ylds(KArgs a) {
     for (int iter = 0;; iter++) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
-        ylds_item(a, itx, smem);
+        ylds_item<false>(a, itx, smem);
     }
 }
 
@@ -963,7 +1064,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) voi
     for (int iter = 0;; iter++) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
-        ylds_item(a, itx, smem);
+        ylds_item<false>(a, itx, smem);
+    }
+}
+
+// The same launch shape with a cut-producing wave beside each replica's wave
+// (two waves per SIMD).
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_ylds_pc(KArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int iter = 0;; iter++) {
+        const int itx = next_item(a, iter);
+        if (itx < 0) break;
+        ylds_item<true>(a, itx, smem);
     }
 }
 
@@ -1024,6 +1136,12 @@ static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
            (size_t)wpb * 64 * (m + 8) * 2;
 }
 
+// + the producer/consumer pairs' cut buffers (two sweeps of ceil(m/4) blocks of
+// 64 uint2) and their flags
+static size_t ylds_pc_lds_bytes(const uavq_plan *pl, int m, int wpb) {
+    return al16(ylds_lds_bytes(pl, m, wpb)) + (size_t)wpb * 2 * ((m + 3) / 4) * 64 * 8 + (size_t)wpb * 4 * 4;
+}
+
 static size_t factored_lds_bytes(const uavq_plan *pl, int m) {
     // + 64: cost-row reads of lanes past m run up to 63 bytes beyond D
     return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64;
@@ -1043,6 +1161,7 @@ bool ylds_fits(const uavq_plan *pl) {
 static bool use_ylds(const uavq_plan *pl) { return pl->variant != UAVQ_VARIANT_ROWMASK && ylds_fits(pl); }
 
 static const void *class_kernel(const uavq_plan *pl, int cls) {
+    if (cls == 1 && use_ylds(pl) && pl->ylds_pc) return (const void *)k_sweep_ylds_pc;
     if (cls == 1 && use_ylds(pl)) return pl->ylds_w1 ? (const void *)k_sweep_ylds_w1 : (const void *)k_sweep_ylds;
     if (cls == 1) return (const void *)k_sweep_factored<1>;
     if (cls == 2) return (const void *)k_sweep_factored<2>;
@@ -1061,17 +1180,22 @@ static int prepare(const uavq_plan *cpl) {
         // one wave per SIMD when every wave of the m <= 64 launch is resident at once
         const int n1 = pl->class_begin[2] - pl->class_begin[1], w1 = pl->waves_per_block[1];
         pl->ylds_w1 = use_ylds(pl) && w1 <= 4 && (int64_t)n1 * w1 <= 4 * (int64_t)pl->cu_count;
+        // and a cut-producing wave beside each replica when the pair still fits (cuts are uint16)
+        pl->ylds_pc = pl->ylds_w1 && !pl->no_producer && pl->Dmax < 65535 &&
+                      ylds_pc_lds_bytes(pl, class_mmax(pl, 1), w1) <= 160 * 1024;
     }
     for (int cls = 1; cls <= kMaxChunks; cls++) {
         if (pl->dense || pl->class_begin[cls + 1] <= pl->class_begin[cls]) continue;
         const int mmax = class_mmax(pl, cls), wpb = pl->waves_per_block[cls];
-        const size_t lds = (cls == 1 && use_ylds(pl)) ? ylds_lds_bytes(pl, mmax, wpb) : factored_lds_bytes(pl, mmax);
+        const bool pc = cls == 1 && use_ylds(pl) && pl->ylds_pc;
+        const size_t lds = pc ? ylds_pc_lds_bytes(pl, mmax, wpb)
+                              : (cls == 1 && use_ylds(pl)) ? ylds_lds_bytes(pl, mmax, wpb) : factored_lds_bytes(pl, mmax);
         if (lds > 160 * 1024)
             return set_error(UAVQ_ETOOBIG, "anneal: LDS need %zu bytes (m = %d, Dmax = %d)", lds, mmax, pl->Dmax);
         const void *k = class_kernel(pl, cls);
         UAVQ_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int nb = 0;
-        UAVQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, 64 * wpb, lds));
+        UAVQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (pc ? 128 : 64) * wpb, lds));
         pl->max_blocks[cls] = std::max(nb, 1);
         pl->lds_class[cls] = lds;
     }
@@ -1096,7 +1220,9 @@ static int launch_class(const uavq_plan *pl, KArgs a, int cls, hipStream_t st) {
     const bool timed = pl->timing && !pl->graph;
     if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls], st));
     const size_t lds = pl->lds_class[cls];
-    if (cls == 1 && use_ylds(pl) && pl->ylds_w1)
+    if (cls == 1 && use_ylds(pl) && pl->ylds_pc)
+        hipLaunchKernelGGL(k_sweep_ylds_pc, dim3(grid), dim3(128 * wpb), lds, st, a);
+    else if (cls == 1 && use_ylds(pl) && pl->ylds_w1)
         hipLaunchKernelGGL(k_sweep_ylds_w1, dim3(grid), dim3(64 * wpb), lds, st, a);
     else if (cls == 1 && use_ylds(pl))
         hipLaunchKernelGGL(k_sweep_ylds, dim3(grid), dim3(64 * wpb), lds, st, a);
@@ -1200,6 +1326,7 @@ const char *uavq_plan_kernel_name(const uavq_plan *pl, int32_t cls) {
     if (pl->dense) return pl->n_inst > 0 && cls == 1 ? "k_sweep_dense" : "";
     if (pl->class_begin[cls + 1] <= pl->class_begin[cls]) return "";
     if (uavq::prepare(pl)) return nullptr;   // the one-wave choice needs the device's CU count
+    if (cls == 1 && uavq::use_ylds(pl) && pl->ylds_pc) return "k_sweep_ylds_pc";
     if (cls == 1 && uavq::use_ylds(pl)) return pl->ylds_w1 ? "k_sweep_ylds_w1" : "k_sweep_ylds";
     return cls == 1 ? "k_sweep_factored<1>" : (cls == 2 ? "k_sweep_factored<2>" : "k_sweep_factored<3>");
 }

@@ -22,6 +22,7 @@ KERNEL_DENSE = 0x1
 VARIANT_ROWMASK = 0x10
 PERSISTENT = 0x20
 GRAPH = 0x40
+VARIANT_NOPRODUCER = 0x80
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
 
@@ -306,7 +307,8 @@ class Plan:
 
     def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
                  T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
-                 rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None):
+                 rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None,
+                 no_producer: bool = False):
         self.qubos = list(qubos)
         n = len(self.qubos)
         arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in self.qubos])
@@ -314,6 +316,7 @@ class Plan:
         assert ids.size == n
         flags = (KERNEL_DENSE if dense else 0) | (VARIANT_ROWMASK if rowmask else 0)
         flags |= (PERSISTENT if persistent else 0) | (GRAPH if graph else 0)
+        flags |= VARIANT_NOPRODUCER if no_producer else 0
         self._tune = tune
         p = _Params(replicas, sweeps, T0, T1, seed, flags, waves_per_block,
                     C.pointer(tune) if tune is not None else None)

@@ -96,6 +96,37 @@ def test_ragged_replicas_and_block_shapes(U, oracle_lib):
                 assert np.array_equal(gi[f], base[f])
 
 
+@pytest.mark.parametrize("variant,kw,kernel", [
+    ("pc", {}, "k_sweep_ylds_pc"),
+    ("w1", {"no_producer": True}, "k_sweep_ylds_w1"),
+    ("ylds", {"wpb": 8}, "k_sweep_ylds"),
+])
+def test_m64_kernel_variants(U, oracle_lib, variant, kw, kernel):
+    """The three m <= 64 sweeps (with a cut-producing wave per replica, one
+    wave per SIMD, several waves per SIMD) against the oracle on every replica,
+    with seeded replicas starting at different sweeps (so producers start and
+    stop at different points of the run), through the hot, middle and frozen
+    parts of a schedule."""
+    g = inputs.grid(7, 7, 0.1, seed=12, inst=40)
+    o = _oracle_for(oracle_lib, g)
+    R, S, T0, T1 = 24, 160, 150.0, 0.5
+    rng = np.random.default_rng(3)
+    x0 = rng.integers(0, 2, size=(R, o.N), dtype=np.uint8)
+    seeded = (np.arange(R) % 3 == 0).astype(np.uint8)
+    start = np.where(seeded == 1, rng.integers(0, S + 1, size=R), 0).astype(np.int32)
+    start[3] = S            # a replica that never sweeps
+    start[6] = S - 1        # and one that sweeps once
+    say(f"case: m<=64 variant {variant} 7x7 R={R} S={S}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, 5, init_x=[x0], seeded=seeded, start_sweep=start, **kw)
+    assert plan.kernel_name(1) == kernel
+    gi = split(U, qs, plan, res)[0]
+    table = oracle_lib.thresholds(T0, T1, S)
+    for r in range(R):
+        ix = x0[[r]] if seeded[r] else None
+        o_r = oracle_lib.anneal(o, S, T0, T1, 5, g.inst_id, [r], init_x=ix, start_sweep=int(start[r]), table=table)
+        compare_replicas(gi, o_r, [r], f"{variant} replica {r}")
+
+
 def test_single_sweep_and_constant_temperature(U, oracle_lib):
     g = inputs.grid(4, 4, 0.0, seed=1, inst=5)
     _check_instance(U, oracle_lib, g, 8, 1, 30.0, 30.0, 2)
