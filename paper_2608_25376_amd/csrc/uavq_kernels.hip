@@ -1561,7 +1561,7 @@ int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *ins
     // on its own kernel's time (events around each class's launch); the
     // variant only concerns class 1.
     const int wpbs[] = {1, 2, 4, 8, 16};
-    const uint32_t variants[] = {0u, UAVQ_VARIANT_ROWMASK};
+    const uint32_t variants[] = {0u, UAVQ_VARIANT_ROWMASK, UAVQ_VARIANT_NOPRODUCER};
     hipStream_t st = nullptr;
     UAVQ_HIP(hipStreamCreate(&st));
     float best_cls[kMaxChunks + 1];
@@ -1579,7 +1579,7 @@ int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *ins
             t.variant_flags = var;
             uavq_anneal_params tp = *p;
             tp.sweeps = trial_sweeps;
-            tp.flags &= ~(uint32_t)(UAVQ_GRAPH | UAVQ_VARIANT_ROWMASK);
+            tp.flags &= ~(uint32_t)(UAVQ_GRAPH | UAVQ_VARIANT_ROWMASK | UAVQ_VARIANT_NOPRODUCER);
             tp.tune = &t;
             uavq_plan *pl = nullptr;
             if (uavq_plan_create(q, n_inst, inst_ids, &tp, &pl) != UAVQ_OK) continue;
