@@ -636,15 +636,15 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     int16_t *sDs = reinterpret_cast<int16_t *>(sdep + al16((size_t)m));
     uint16_t *Yall = reinterpret_cast<uint16_t *>(sDs + 2 * 64 * (size_t)m);
     uint16_t *Yw = Yall + (size_t)slot * 64 * (m + 8);   // Y_t[c] at Yw[(t-1)*64 + c], t = 1..m+8
+    // per slot, 2P R_t for t = 1..m at index t-1 (68 entries: blocks read four at a time, 0 past m)
+    int *Rall = reinterpret_cast<int *>(smem + al16(reinterpret_cast<uint8_t *>(Yall + (size_t)ncons * 64 * (m + 8)) - smem));
+    int *Rw = Rall + (size_t)slot * 68;
     // PC: per slot, cuts of two sweeps (by parity) [2][NB][64] as four uint16
     // per lane and block, then per slot and parity the flags "cuts valid" and
     // "the sweep had a draw"
-    uint2 *cutbuf = reinterpret_cast<uint2 *>(smem + al16(reinterpret_cast<uint8_t *>(Yall + (size_t)ncons * 64 * (m + 8)) - smem));
+    uint2 *cutbuf = reinterpret_cast<uint2 *>(Rall + (size_t)ncons * 68);
     int *pc_valid = reinterpret_cast<int *>(cutbuf + (size_t)ncons * 2 * NB * 64);
     int *pc_drew = pc_valid + 2 * ncons;
-    // PC: per slot, 2P R_t for t = 1..m at index t-1 (68 entries: blocks read four at a time, 0 past m)
-    int *Rall = pc_drew + 2 * ncons;
-    int *Rw = Rall + (size_t)slot * 68;
     __shared__ int s_first_sh;
 
     {
@@ -713,7 +713,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             cm |= (uint64_t)x << (t - 1);
             Cc += x;
             const int R = __popcll(row);
-            if (PC && L == 0) Rw[t - 1] = twoP * R;
+            if (L == 0) Rw[t - 1] = twoP * R;
             rowterm += (int64_t)d.P * R * (R - 1) - (int64_t)twoP * R;
             lane_e += x * Yp;
             if (t == m && d.closed) lane_e += x * dep;
@@ -732,7 +732,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         // boundary rows: step m+1 is the return leg (start-cell costs, or 0 for
         // an open path), steps beyond it are zero; reads past m need no test
         for (int t = m + 1; t <= m + 8; t++) Yw[(t - 1) * 64 + L] = (uint16_t)(t == m + 1 && d.closed ? dep : 0);
-        if (PC && L == 0)
+        if (L == 0)
             for (int t = m + 1; t <= 68; t++) Rw[t - 1] = 0;
     }
 
@@ -789,7 +789,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             const bool cv = PC && pc_valid[2 * slot + (s & 1)] != 0;
             const uint2 *cbs = cutbuf + (size_t)(2 * slot + (s & 1)) * NB * 64 + L;
             uint2 cwn = PC ? cbs[0] : make_uint2(0u, 0u);   // the next block's cuts, read a block ahead
-            int4 cqn = PC ? *reinterpret_cast<const int4 *>(Rw) : make_int4(0, 0, 0, 0);   // and its 2P R_t
+            int4 cqn = *reinterpret_cast<const int4 *>(Rw);   // the next block's 2P R_t
             const uint32_t ndl0 = ndraw_lane;
             // Steps are visited in blocks of four (the Philox blocks); Yv[k] holds
             // Y_{t0-1+k} for the block starting at step t0, and the travel rows of
@@ -813,7 +813,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 uint2 cw = cwn;
                 if (PC) cwn = cbs[min(((t0 - 1) >> 2) + 1, NB - 1) * 64];
                 const int4 cq = cqn;
-                if (PC) cqn = *reinterpret_cast<const int4 *>(Rw + t0 + 3);
+                cqn = *reinterpret_cast<const int4 *>(Rw + t0 + 3);
                 const int cqa[4] = {cq.x, cq.y, cq.z, cq.w};
                 bool have_ct = cv;
                 // without the producer's cuts, draw them here (kept out of line: rare)
@@ -838,17 +838,14 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                     // 4P - 2P R_t - A for x = 1, A = Y_{t-1} + Y_{t+1} + 2P (C_c - 1)
                     const uint32_t xbits = (uint32_t)(cm >> (t0 - 1));
                     bool xb[4];
-                    uint64_t rm[4];
                     int A[4], dEs[4];
 #pragma unroll
                     for (int i = 0; i < 4; i++) xb[i] = (xbits >> i) & 1u;
 #pragma unroll
-                    for (int i = 0; i < 4; i++) rm[i] = PC ? 0ull : ballot64(xb[i]);
-#pragma unroll
                     for (int i = 0; i < 4; i++) A[i] = Yv[i] + Yv[i + 2] + Kc;
 #pragma unroll
                     for (int i = 0; i < 4; i++) {
-                        const int c1 = PC ? cqa[i] : __builtin_amdgcn_readfirstlane(twoP * (int)__popcll(rm[i]));
+                        const int c1 = cqa[i];
                         dEs[i] = xb[i] ? (2 * twoP - c1) - A[i] : A[i] + c1;
                     }
                     const int mn = min(min(dEs[0], dEs[1]), min(dEs[2], dEs[3]));
@@ -908,7 +905,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                         if (t > m) break;
                         const bool xb = (cm >> (t - 1)) & 1ull;
                         const uint64_t rmask = ballot64(xb);
-                        const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) + (PC ? cqa[i] : twoP * (int)__popcll(rmask));
+                        const int h = Yv[i] + Yv[i + 2] + Kc - (xb ? 2 * twoP : 0) + cqa[i];
                         const int dE0 = xb ? -h : h;            // dE against the state at the step start
                         const int dplus = xb ? -twoP : twoP;    // change of dE per net 1 gained by step t
                         uint64_t openm = lanes_m, accd = 0;
@@ -969,7 +966,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                         // draws of this step, counted per lane (lanes >= m are dropped at the end)
                         ndraw_lane += (uint32_t)(dEv - 1) < (uint32_t)(dcut - 1) ? 1u : 0u;
                         if (accd) {
-                            if (PC && L == 0) Rw[t - 1] = twoP * (int)__popcll(rmask ^ accd);   // the step's new R_t
+                            if (L == 0) Rw[t - 1] = twoP * (int)__popcll(rmask ^ accd);   // the step's new R_t
                             nacc_s += (uint32_t)__popcll(accd);
                             const int inA = (int)((accd >> L) & 1ull);   // this lane's site was flipped
                             cm ^= (uint64_t)inA << (t - 1);
@@ -1142,16 +1139,16 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a) {
 
 // ------------------------------------------------------------- launchers --
 static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
-    // per replica: travel rows of steps 1..m plus 8 boundary rows, 64 int16 each
-    return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 256 * (size_t)m +
-           (size_t)wpb * 64 * (m + 8) * 2;
+    // per replica: travel rows of steps 1..m plus 8 boundary rows, 64 int16 each, and 68 step counts
+    return al16(4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 256 * (size_t)m +
+                (size_t)wpb * 64 * (m + 8) * 2) +
+           (size_t)wpb * 68 * 4;
 }
 
 // + the producer/consumer pairs' cut buffers (two sweeps of ceil(m/4) blocks of
-// 64 uint2), their flags and the 2P R_t of every step
+// 64 uint2) and their flags
 static size_t ylds_pc_lds_bytes(const uavq_plan *pl, int m, int wpb) {
-    return al16(ylds_lds_bytes(pl, m, wpb)) + (size_t)wpb * 2 * ((m + 3) / 4) * 64 * 8 + (size_t)wpb * 4 * 4 +
-           (size_t)wpb * 68 * 4;
+    return ylds_lds_bytes(pl, m, wpb) + (size_t)wpb * 2 * ((m + 3) / 4) * 64 * 8 + (size_t)wpb * 4 * 4;
 }
 
 static size_t factored_lds_bytes(const uavq_plan *pl, int m) {
