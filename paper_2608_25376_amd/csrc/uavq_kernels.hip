@@ -25,10 +25,12 @@
 // dE each site was visited with is rebuilt at the step end (draw counts,
 // energy); Y_t takes the cost rows of the flipped cells.
 //
-// m <= 64 (k_sweep_ylds): lane c holds the column of cell c as a step mask,
-// the travel rows Y_t live in LDS per replica, and blocks of four steps are
-// first evaluated speculatively against the block-start state, which
-// finishes most blocks at low temperature without the walk.
+// m <= 64 (k_sweep_ylds*): lane c holds the column of cell c as a step mask,
+// the travel rows Y_t and the step terms 2P R_t live in LDS per replica, and
+// blocks of four steps are first evaluated speculatively against the
+// block-start state, which finishes most blocks at low temperature without
+// the walk.  When one replica runs per SIMD (k_sweep_ylds_pc) a second wave
+// per replica computes the next sweep's random words and acceptance cuts.
 // m <= 192 (k_sweep_factored): lane L holds the cell masks of steps
 // L + 1 + 64 j (bits = cells) and the occupation count of cells L + 64 j, and
 // travel rows are rebuilt from the neighbouring steps' masks.
