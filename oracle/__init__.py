@@ -48,7 +48,7 @@ def lib():
         L.orc_dmax.argtypes = [dbl]
         L.orc_dmax.restype = i32
         L.orc_thresholds.argtypes = [dbl, dbl, i32, i32, P(u32)]
-        L.orc_anneal.argtypes = [i32, P(i32), P(i32), i64, i32, i32, P(u32), u32, u32, i32, P(i32),
+        L.orc_anneal.argtypes = [i32, P(i32), P(i32), i32, P(i32), i64, i32, i32, P(u32), u32, u32, i32, P(i32),
                                  P(u8), P(i32), i32, P(u8), P(i64), P(i64), P(i32), P(u8), P(u64),
                                  P(u64), P(i64), i32]
         L.orc_anneal.restype = i32
@@ -187,8 +187,9 @@ def anneal(q, sweeps, T0, T1, seed, inst, replicas, init_x=None, start_sweep=Non
            threads=0, table=None):
     """Run replicas ``replicas`` (list of replica ids) of instance id ``inst``.
 
+    Uses the stored J when the instance has one, otherwise evaluates every
+    coefficient from its definition where it is needed (large fields).
     Returns a dict of numpy arrays indexed like ``replicas``."""
-    assert q.J is not None, "the oracle annealer uses the dense J built from its definition"
     reps = np.ascontiguousarray(replicas, dtype=np.int32)
     n = reps.size
     N = q.N
@@ -206,7 +207,8 @@ def anneal(q, sweeps, T0, T1, seed, inst, replicas, init_x=None, start_sweep=Non
         draws=np.zeros(n, np.uint64), mismatches=np.zeros(n, np.int64))
     thr = np.ascontiguousarray(thr, dtype=np.uint32)
     rc = lib().orc_anneal(
-        q.m, _p(q.J, C.c_int32), _p(q.b, C.c_int32), q.c0, sweeps, dmax, _p(thr, C.c_uint32),
+        q.m, _p(q.J, C.c_int32), _p(q.W, C.c_int32), q.P, _p(q.b, C.c_int32), q.c0, sweeps, dmax,
+        _p(thr, C.c_uint32),
         seed, inst, n, _p(reps, C.c_int32), _p(ix, C.c_uint8), _p(ss, C.c_int32), check_every,
         _p(out["final_x"], C.c_uint8), _p(out["final_E"], C.c_int64), _p(out["best_E"], C.c_int64),
         _p(out["best_sweep"], C.c_int32), _p(out["best_x"], C.c_uint8), _p(out["accepts"], C.c_uint64),

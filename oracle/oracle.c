@@ -17,9 +17,10 @@
  *     schedule and random-number addressing below are this project's reading),
  *   - exact checkers: 2^N enumeration, brute force over tours, Held-Karp DP.
  *
- * Everything is written for clarity: dense int32 J built from its definition,
- * O(N) field updates, no blocking or fusion.  The only parallelism is an
- * OpenMP loop over independent replicas.
+ * Everything is written for clarity: dense int32 J built from its definition
+ * (or, for fields too large to store it, each coefficient evaluated from the
+ * same definition where it is used), O(N) field updates, no blocking or
+ * fusion.  The only parallelism is an OpenMP loop over independent replicas.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -220,6 +221,28 @@ int64_t orc_qubo_energy(int32_t N, const int32_t *J, const int32_t *b, int64_t c
     return e;
 }
 
+/* J_kl from the stored matrix, or from its definition when none is stored.  */
+static inline int32_t J_at(const int32_t *J, int32_t N, int32_t m, const int32_t *W, int32_t P,
+                           int32_t k, int32_t l)
+{
+    return J ? J[(int64_t)k * N + l] : orc_J(m, W, P, k, l);
+}
+
+/* E(x) = c0 + sum_k b_k x_k + sum_{k<l} J_kl x_k x_l, J stored or not. */
+static int64_t qubo_energy_any(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const int32_t *b,
+                               int64_t c0, const uint8_t *x)
+{
+    int32_t N = m * m;
+    int64_t e = c0;
+    for (int32_t k = 0; k < N; k++) {
+        if (!x[k]) continue;
+        e += b[k];
+        for (int32_t l = k + 1; l < N; l++)
+            if (x[l]) e += J_at(J, N, m, W, P, k, l);
+    }
+    return e;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Schedule and acceptance thresholds.                                       */
 /* T_s = T0 (T1/T0)^(s/(S-1)) (geometric; S = 1 gives T0).                    */
@@ -272,21 +295,23 @@ void orc_thresholds(double T0, double T1, int32_t S, int32_t Dmax, uint32_t *thr
 /*       on accept: x_k ^= 1, h_l += (x_k' - x_k) J_kl for l != k, E += dE   */
 /*     at the end of the sweep: if E < best_E then best_E, best_sweep, best_x */
 /* ------------------------------------------------------------------------ */
-static int64_t field_energy_mismatch(int32_t N, const int32_t *J, const int32_t *b, int64_t c0,
-                                     const uint8_t *x, const int32_t *h, int64_t E)
+static int64_t field_energy_mismatch(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const int32_t *b,
+                                     int64_t c0, const uint8_t *x, const int32_t *h, int64_t E)
 {
+    int32_t N = m * m;
     int64_t bad = 0;
     for (int32_t k = 0; k < N; k++) {
         int64_t v = b[k];
         for (int32_t l = 0; l < N; l++)
-            if (l != k && x[l]) v += J[(int64_t)k * N + l];
+            if (l != k && x[l]) v += J_at(J, N, m, W, P, k, l);
         if (v != h[k]) bad++;
     }
-    if (orc_qubo_energy(N, J, b, c0, x) != E) bad++;
+    if (qubo_energy_any(m, J, W, P, b, c0, x) != E) bad++;
     return bad;
 }
 
-int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *b, int64_t c0,
+/* J may be NULL: then every coefficient comes from orc_J(m, W, P, ., .). */
+int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const int32_t *b, int64_t c0,
                    int32_t S, int32_t Dmax, const uint32_t *thr,
                    uint32_t seed, uint32_t inst, int32_t n_rep, const int32_t *rep_ids,
                    const uint8_t *init_x, const int32_t *start_sweep, int32_t check_every,
@@ -312,10 +337,10 @@ int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *b, int64_t c0,
         for (int32_t k = 0; k < N; k++) {
             int32_t v = b[k];
             for (int32_t l = 0; l < N; l++)
-                if (l != k && x[l]) v += J[(int64_t)k * N + l];
+                if (l != k && x[l]) v += J_at(J, N, m, W, P, k, l);
             h[k] = v;
         }
-        int64_t E = orc_qubo_energy(N, J, b, c0, x);
+        int64_t E = qubo_energy_any(m, J, W, P, b, c0, x);
         int64_t bE = INT64_MAX;
         int32_t bs = -1;
         uint64_t acc = 0, drw = 0;
@@ -344,7 +369,7 @@ int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *b, int64_t c0,
                     int32_t delta = x[k] ? -1 : 1;
                     x[k] ^= 1;
                     for (int32_t l = 0; l < N; l++)
-                        if (l != k) h[l] += delta * J[(int64_t)k * N + l];
+                        if (l != k) h[l] += delta * J_at(J, N, m, W, P, k, l);
                     E += dE;
                     acc++;
                 }
@@ -355,7 +380,7 @@ int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *b, int64_t c0,
                 memcpy(bx, x, (size_t)N);
             }
             if (check_every > 0 && ((s - s0 + 1) % check_every == 0 || s == S - 1))
-                bad += field_energy_mismatch(N, J, b, c0, x, h, E);
+                bad += field_energy_mismatch(m, J, W, P, b, c0, x, h, E);
         }
         final_E[i] = E;
         best_E[i] = bE;

@@ -271,6 +271,24 @@ def test_anneal_zero_temperature_descent(oracle_lib):
     assert (np.diff(Es, axis=0) <= 0).all()
 
 
+def test_anneal_without_stored_J(oracle_lib):
+    """Fields too large for a dense J are annealed with every coefficient
+    evaluated from its definition where it is used; on fields small enough for
+    both, the two give the same trajectories, and the incrementally kept fields
+    still equal a recomputation (mismatch counter 0)."""
+    for rows, cols, dens, inst, closed in [(3, 4, 0.0, 1, True), (4, 4, 0.2, 2, False), (5, 5, 0.1, 3, True)]:
+        g = inputs.grid(rows, cols, dens, seed=6, inst=inst)
+        qd = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed)
+        qf = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed, dense=False)
+        assert qf.J is None and qf.c0 == qd.c0 and (qf.b == qd.b).all()
+        reps = [0, 3, 8]
+        a = oracle_lib.anneal(qd, 40, 90.0, 0.5, 7, inst, reps, check_every=5)
+        b = oracle_lib.anneal(qf, 40, 90.0, 0.5, 7, inst, reps, check_every=5)
+        for f in ("final_x", "final_E", "best_E", "best_sweep", "best_x", "accepts", "draws"):
+            assert np.array_equal(a[f], b[f]), f
+        assert (b["mismatches"] == 0).all() and (a["mismatches"] == 0).all()
+
+
 def test_anneal_checkpoint_split(oracle_lib):
     """The stream is addressed by (instance, replica, sweep, site), so stopping
     after S1 sweeps and resuming from that state at sweep S1 gives the same
