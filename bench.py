@@ -268,7 +268,7 @@ def main():
     sweep_avg = float(np.mean(sweep_ms)) if sweep_ms else ms_per_step
     achieved = ops / (sweep_avg * 1e-3)
     value = attempts / (ms_per_step * 1e-3)
-    kernels = [k for k in (plan.kernel_name(c) for c in (1, 2, 3)) if k]
+    kernels = [k for k in (plan.kernel_name(c) for c in range(1, uavq.CHUNK_CLASSES + 1)) if k]
     kernel = "+".join(kernels)
 
     res = {

@@ -31,7 +31,7 @@
 // block-start state, which finishes most blocks at low temperature without
 // the walk.  When one replica runs per SIMD (k_sweep_ylds_pc) a second wave
 // per replica computes the next sweep's random words and acceptance cuts.
-// m <= 192 (k_sweep_factored): lane L holds the cell masks of steps
+// m <= 256 (k_sweep_factored): lane L holds the cell masks of steps
 // L + 1 + 64 j (bits = cells) and the occupation count of cells L + 64 j, and
 // travel rows are rebuilt from the neighbouring steps' masks.
 // The cost matrix D, the start-cell costs and one row of the acceptance table
@@ -594,6 +594,19 @@ __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
         factored_item<NJ>(a, itx, smem);
+    }
+}
+
+// The fourth chunk class (m <= 256) holds more state per lane than a
+// 1024-thread block's register budget allows: built for at most
+// kWideMaxWaves waves per block and two waves per SIMD.
+__global__ __launch_bounds__(64 * kWideMaxWaves) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_sweep_factored4(
+    KArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int iter = 0;; iter++) {
+        const int itx = next_item(a, iter);
+        if (itx < 0) break;
+        factored_item<4>(a, itx, smem);
     }
 }
 
@@ -1176,7 +1189,8 @@ static const void *class_kernel(const uavq_plan *pl, int cls) {
     if (cls == 1 && use_ylds(pl)) return pl->ylds_w1 ? (const void *)k_sweep_ylds_w1 : (const void *)k_sweep_ylds;
     if (cls == 1) return (const void *)k_sweep_factored<1>;
     if (cls == 2) return (const void *)k_sweep_factored<2>;
-    return (const void *)k_sweep_factored<3>;
+    if (cls == 3) return (const void *)k_sweep_factored<3>;
+    return (const void *)k_sweep_factored4;
 }
 
 // Kernel attributes and occupancy, once per plan and outside any stream
@@ -1241,8 +1255,10 @@ static int launch_class(const uavq_plan *pl, KArgs a, int cls, hipStream_t st) {
         hipLaunchKernelGGL(k_sweep_factored<1>, dim3(grid), dim3(64 * wpb), lds, st, a);
     else if (cls == 2)
         hipLaunchKernelGGL(k_sweep_factored<2>, dim3(grid), dim3(64 * wpb), lds, st, a);
-    else
+    else if (cls == 3)
         hipLaunchKernelGGL(k_sweep_factored<3>, dim3(grid), dim3(64 * wpb), lds, st, a);
+    else
+        hipLaunchKernelGGL(k_sweep_factored4, dim3(grid), dim3(64 * wpb), lds, st, a);
     UAVQ_HIP(hipGetLastError());
     if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls + 1], st));
     return UAVQ_OK;
@@ -1339,7 +1355,8 @@ const char *uavq_plan_kernel_name(const uavq_plan *pl, int32_t cls) {
     if (uavq::prepare(pl)) return nullptr;   // the one-wave choice needs the device's CU count
     if (cls == 1 && uavq::use_ylds(pl) && pl->ylds_pc) return "k_sweep_ylds_pc";
     if (cls == 1 && uavq::use_ylds(pl)) return pl->ylds_w1 ? "k_sweep_ylds_w1" : "k_sweep_ylds";
-    return cls == 1 ? "k_sweep_factored<1>" : (cls == 2 ? "k_sweep_factored<2>" : "k_sweep_factored<3>");
+    return cls == 1 ? "k_sweep_factored<1>"
+                    : (cls == 2 ? "k_sweep_factored<2>" : (cls == 3 ? "k_sweep_factored<3>" : "k_sweep_factored4"));
 }
 
 int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
@@ -1518,8 +1535,8 @@ static bool cache_lookup(const char *path, const std::string &key, uavq_tune *t)
         if (std::string(q1 + 1, q2) != key) continue;
         uavq_tune v{};
         unsigned var = 0;
-        if (sscanf(q2 + 1, ": {\"wpb\": [%d, %d, %d], \"variant\": %u, \"ms\": %f}", &v.waves_per_block[1],
-                   &v.waves_per_block[2], &v.waves_per_block[3], &var, &v.trial_ms) == 5) {
+        if (sscanf(q2 + 1, ": {\"wpb\": [%d, %d, %d, %d], \"variant\": %u, \"ms\": %f}", &v.waves_per_block[1],
+                   &v.waves_per_block[2], &v.waves_per_block[3], &v.waves_per_block[4], &var, &v.trial_ms) == 6) {
             v.variant_flags = var;
             *t = v;
             found = true;
@@ -1545,8 +1562,9 @@ static void cache_store(const char *path, const std::string &key, const uavq_tun
         fclose(f);
     }
     char buf[512];
-    snprintf(buf, sizeof buf, "\"%s\": {\"wpb\": [%d, %d, %d], \"variant\": %u, \"ms\": %.4f}", key.c_str(),
-             t.waves_per_block[1], t.waves_per_block[2], t.waves_per_block[3], (unsigned)t.variant_flags, t.trial_ms);
+    snprintf(buf, sizeof buf, "\"%s\": {\"wpb\": [%d, %d, %d, %d], \"variant\": %u, \"ms\": %.4f}", key.c_str(),
+             t.waves_per_block[1], t.waves_per_block[2], t.waves_per_block[3], t.waves_per_block[4],
+             (unsigned)t.variant_flags, t.trial_ms);
     keep.push_back(buf);
     std::string tmp = std::string(path) + ".tmp";
     FILE *f = fopen(tmp.c_str(), "w");

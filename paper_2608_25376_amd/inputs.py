@@ -79,6 +79,9 @@ def workload(name: str) -> Workload:
     if name == "grid12x12":
         return Workload(name, [grid(12, 12)], 4096, 4000, 200.0, 0.5, 1,
                         "12x12, no obstacles, 143 free cells, 20449 vars")
+    if name == "grid16x16":
+        return Workload(name, [grid(16, 16)], 4096, 1000, 200.0, 0.5, 1,
+                        "16x16, no obstacles, 255 free cells, 65025 vars (the largest factored class)")
     if name == "batch256":
         return Workload(name, batch(256, 1), 256, 2000, 200.0, 0.5, 1,
                         "256 instances, side U{4..10}, density U[0,0.2]")

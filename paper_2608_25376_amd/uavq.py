@@ -23,6 +23,7 @@ VARIANT_ROWMASK = 0x10
 PERSISTENT = 0x20
 GRAPH = 0x40
 VARIANT_NOPRODUCER = 0x80
+CHUNK_CLASSES = 4          # sweep kernel classes by ceil(m / 64); m <= 256
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
 
@@ -47,7 +48,7 @@ class _QuboInfo(C.Structure):
 
 class Tune(C.Structure):
     """Launch shape chosen by autotune (per chunk class c = ceil(m/64))."""
-    _fields_ = [("waves_per_block", C.c_int32 * 4), ("variant_flags", C.c_uint32), ("trial_ms", C.c_float)]
+    _fields_ = [("waves_per_block", C.c_int32 * 5), ("variant_flags", C.c_uint32), ("trial_ms", C.c_float)]
 
     def __repr__(self):
         return (f"Tune(waves_per_block={list(self.waves_per_block)[1:]}, variant={self.variant_flags:#x}, "
@@ -351,7 +352,7 @@ class Plan:
         _check(lib().uavq_plan_set_timing(self._h, 1 if enable else 0))
 
     def kernel_name(self, cls=1):
-        """Sweep kernel launched for chunk class cls (1: m <= 64, 2: <= 128, 3: <= 192); '' if unused."""
+        """Sweep kernel launched for chunk class cls (1: m <= 64, 2: <= 128, 3: <= 192, 4: <= 256); '' if unused."""
         v = lib().uavq_plan_kernel_name(self._h, int(cls))
         if v is None:
             raise UavqError(-1, lib().uavq_last_error().decode())

@@ -73,6 +73,36 @@ def test_multi_chunk_rows(U, oracle_lib, side, dens, inst):
     _check_instance(U, oracle_lib, g, 9, 12, 200.0, 0.5, 3)
 
 
+@pytest.mark.parametrize("side,dens,inst", [(14, 0.0, 12), (16, 0.05, 13)])
+def test_fourth_class_fields(U, oracle_lib, side, dens, inst):
+    """192 < m <= 256 (up to 65,025 variables): the fourth chunk class's kernel
+    against the oracle, which evaluates every coefficient from its definition
+    (a stored J would take gigabytes), on two replicas over a short hot
+    schedule; every replica's energy agrees with the MFMA recomputation."""
+    g = inputs.grid(side, side, dens, seed=2, inst=inst)
+    assert 192 < g.n_free <= 256
+    m = g.n_free
+    R, S, T0, T1 = 6, 5, 150.0, 50.0
+    # the compared replicas start from random tours (the oracle's cost is then its
+    # O(N) field updates per accepted flip, not the clean-up of random bits)
+    rng = np.random.default_rng(inst)
+    x0 = np.zeros((R, m * m), np.uint8)
+    for r in range(R):
+        X = np.zeros((m, m), np.uint8)
+        X[np.arange(m), rng.permutation(m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = np.array([1, 0, 0, 1, 0, 1], np.uint8)
+    say(f"case: fourth class {side}x{side} m={m} R={R} S={S}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, 3, init_x=[x0], seeded=seeded, check_E=True)
+    assert plan.kernel_name(4) == "k_sweep_factored4"
+    gi = split(U, qs, plan, res)[0]
+    assert np.array_equal(gi["check_E"], gi["final_E"])
+    o = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, dense=False)
+    reps = [0, R - 1]
+    orc = oracle_lib.anneal(o, S, T0, T1, 3, g.inst_id, reps, init_x=x0[reps], threads=2)
+    compare_replicas(gi, orc, reps, f"{side}x{side}")
+
+
 @pytest.mark.parametrize("rows,cols,dens,inst,closed", [
     (1, 2, 0.0, 0, True), (3, 3, 0.0, 1, True), (5, 5, 0.0, 3, False), (8, 8, 0.1, 0, True)])
 def test_rowmask_variant(U, oracle_lib, rows, cols, dens, inst, closed):
