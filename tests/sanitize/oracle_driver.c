@@ -1,0 +1,102 @@
+/* Drives the oracle (instance, costs, QUBO, energies, schedule, annealing with
+ * and without a stored J, enumeration, brute force, Held-Karp, seed sampling)
+ * for a build under AddressSanitizer and UndefinedBehaviorSanitizer. */
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+uint32_t orc_init_bit(uint32_t seed, uint32_t inst, uint32_t r, int t, int c);
+int32_t orc_free_cells(int32_t rows, int32_t cols, int32_t depot, const uint8_t *nofly, int32_t *F);
+int32_t orc_cost_matrix(int32_t cols, int32_t depot, int32_t m, const int32_t *F, int32_t scale, int32_t *W);
+int64_t orc_literal_energy(int32_t m, const int32_t *W, int32_t P, int32_t closed, const uint8_t *x);
+void orc_build_qubo(int32_t m, const int32_t *W, int32_t P, int32_t closed, int32_t *J, int32_t *b, int64_t *c0);
+int64_t orc_qubo_energy(int32_t N, const int32_t *J, const int32_t *b, int64_t c0, const uint8_t *x);
+int32_t orc_dmax(double T0);
+void orc_thresholds(double T0, double T1, int32_t S, int32_t Dmax, uint32_t *thr);
+int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const int32_t *b, int64_t c0,
+                   int32_t S, int32_t Dmax, const uint32_t *thr, uint32_t seed, uint32_t inst, int32_t n_rep,
+                   const int32_t *rep_ids, const uint8_t *init_x, const int32_t *start_sweep, int32_t check_every,
+                   uint8_t *final_x, int64_t *final_E, int64_t *best_E, int32_t *best_sweep, uint8_t *best_x,
+                   uint64_t *accepts, uint64_t *draws, int64_t *mismatches, int32_t n_threads);
+int32_t orc_enum_min(int32_t m, const int32_t *J, const int32_t *b, int64_t c0, int64_t *min_E, int64_t *n_min,
+                     uint8_t *argmin, int64_t *min_infeasible);
+int32_t orc_tour_brute(int32_t m, const int32_t *W, int32_t closed, int64_t *best, int64_t *n_opt);
+int64_t orc_held_karp(int32_t m, const int32_t *W, int32_t closed);
+int32_t orc_sample_seed(int32_t m, const uint16_t *q, uint32_t seed, uint32_t inst, uint32_t r, uint8_t *x);
+
+#define CHECK(c)                                                                \
+    do {                                                                        \
+        if (!(c)) {                                                             \
+            fprintf(stderr, "check failed: %s (line %d)\n", #c, __LINE__);     \
+            return 1;                                                           \
+        }                                                                       \
+    } while (0)
+
+static int field(int rows, int cols, int closed, int with_J)
+{
+    uint8_t *nf = calloc((size_t)rows * cols, 1);
+    int32_t *F = malloc(sizeof(int32_t) * (size_t)rows * cols);
+    int32_t m = orc_free_cells(rows, cols, 0, nf, F);
+    CHECK(m == rows * cols - 1);
+    int32_t N = m * m;
+    int32_t *W = malloc(sizeof(int32_t) * (size_t)(m + 1) * (m + 1));
+    int32_t wmax = orc_cost_matrix(cols, 0, m, F, 10, W);
+    int32_t P = 2 * wmax;
+    int32_t *b = malloc(sizeof(int32_t) * (size_t)N);
+    int32_t *J = with_J ? malloc(sizeof(int32_t) * (size_t)N * N) : NULL;
+    int64_t c0 = 0;
+    orc_build_qubo(m, W, P, closed, J, b, &c0);
+    uint8_t *x = calloc((size_t)N, 1);
+    for (int32_t t = 0; t < m; t++) x[t * m + (t * 7 + 3) % m] = 1;
+    int64_t lit = orc_literal_energy(m, W, P, closed, x);
+    if (J) CHECK(orc_qubo_energy(N, J, b, c0, x) == lit);
+
+    const int32_t S = 12, n = 3;
+    int32_t Dmax = orc_dmax(80.0);
+    uint32_t *thr = malloc(sizeof(uint32_t) * (size_t)S * (Dmax + 1));
+    orc_thresholds(80.0, 0.5, S, Dmax, thr);
+    int32_t reps[3] = {0, 4, 9}, start[3] = {0, 3, S};
+    uint8_t *fx = malloc((size_t)n * N), *bx = malloc((size_t)n * N);
+    int64_t fE[3], bE[3], mis[3];
+    int32_t bs[3];
+    uint64_t acc[3], drw[3];
+    CHECK(orc_anneal(m, J, W, P, b, c0, S, Dmax, thr, 5, 2, n, reps, NULL, start, 4, fx, fE, bE, bs, bx, acc, drw,
+                     mis, 1) == 0);
+    for (int i = 0; i < n; i++) CHECK(mis[i] == 0);
+
+    /* marginals: m cells x 128 steps of uint16 weights */
+    uint16_t *q = malloc(sizeof(uint16_t) * (size_t)m * 128);
+    for (int32_t k = 0; k < m * 128; k++) q[k] = (uint16_t)(1 + (k * 37) % 500);
+    CHECK(orc_sample_seed(m, q, 9, 2, 1, x) == 0);
+    for (int32_t t = 0; t < m; t++) {
+        int32_t ones = 0;
+        for (int32_t c = 0; c < m; c++) ones += x[t * m + c];
+        CHECK(ones == 1);
+    }
+    if (m <= 9) {
+        int64_t best = 0, nopt = 0;
+        CHECK(orc_tour_brute(m, W, closed, &best, &nopt) == 0);
+        CHECK(orc_held_karp(m, W, closed) == best);
+    }
+    free(nf); free(F); free(W); free(b); free(J); free(x); free(thr); free(fx); free(bx); free(q);
+    return 0;
+}
+
+int main(void)
+{
+    if (field(3, 3, 1, 1) || field(3, 4, 0, 1) || field(4, 4, 1, 0) || field(6, 6, 1, 0)) return 1;
+    /* 2^9 enumeration on the 2x2 field */
+    {
+        int32_t F[4], W[16], b[9], J[81];
+        uint8_t nf[4] = {0, 0, 0, 0}, arg[9];
+        int32_t m = orc_free_cells(2, 2, 0, nf, F);
+        CHECK(m == 3);
+        int32_t wmax = orc_cost_matrix(2, 0, m, F, 10, W);
+        int64_t c0 = 0, mn = 0, nmin = 0, minf = 0;
+        orc_build_qubo(m, W, 2 * wmax, 1, J, b, &c0);
+        CHECK(orc_enum_min(m, J, b, c0, &mn, &nmin, arg, &minf) == 0 && mn < minf);
+    }
+    printf("oracle driver: clean\n");
+    return 0;
+}
