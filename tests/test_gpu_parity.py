@@ -128,6 +128,8 @@ def test_ragged_replicas_and_block_shapes(U, oracle_lib):
 
 @pytest.mark.parametrize("variant,kw,kernel", [
     ("pc", {}, "k_sweep_ylds_pc"),
+    ("pc_persistent", {"persistent": True}, "k_sweep_ylds_pc"),
+    ("pc_wpb2", {"wpb": 2}, "k_sweep_ylds_pc"),
     ("w1", {"no_producer": True}, "k_sweep_ylds_w1"),
     ("ylds", {"wpb": 8}, "k_sweep_ylds"),
 ])
