@@ -22,9 +22,10 @@ if ROOT not in sys.path:
 # MI355X published figures and the integer-VALU peak derived from unit counts:
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3e12 int32 lane-ops/s.
 PEAK_ALU_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic integer operations of the structured Metropolis step
-# ("Roofline"): per attempted flip, per random draw, per
-# accepted flip (plus m for the O(m) travel-row update).
+# Algorithmic integer operations of the structured Metropolis step: per
+# attempted flip (form h from R_t, C_c, x and two travel rows; sign; two
+# compares), per random draw (a quarter of a Philox4x32-10 call, a table read,
+# a compare) and per accepted flip (plus m for the O(m) travel-row update).
 OPS_PER_ATTEMPT = 11
 OPS_PER_DRAW = 27
 OPS_PER_ACCEPT_BASE = 5
@@ -204,8 +205,9 @@ def cpu_baseline(w, q_gpu_m, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              f"(the annealer shards by instance/replica with no communication; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the annealer runs on one GPU; --gpus {args.gpus} is not supported "
+              f"(it would shard by instance and replica, with one reduction of per-instance bests at the end)",
+              file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
