@@ -96,6 +96,25 @@ def aux_measurements(args):
                           "kernel": "k_energy_refresh", "config": {"workload": name, "m": q.m, "states": w.replicas},
                           "ms_per_call": ms, "ops_per_call": ops, "peak": PEAK_INT8_OPS,
                           "frac": ops / (ms * 1e-3) / PEAK_INT8_OPS}), flush=True)
+    # time to result with UAVQ_STOP_FROZEN: the same anneals, identical outputs, frozen sweeps skipped
+    # (a wall time, not a throughput: the skipped sweeps are not evaluated)
+    for name in ("grid8x8_nofly0.1", "grid12x12"):
+        w = inputs.workload(name)
+        qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in w.grids]
+        row = {"metric": "ms per anneal, replicas stop once frozen", "unit": "ms", "higher_is_better": False,
+               "config": {"workload": name, "replicas": w.replicas, "sweeps": w.sweeps}}
+        outs = {}
+        for stop in (False, True):
+            plan = uavq.Plan(qs, [g.inst_id for g in w.grids], w.replicas, w.sweeps, w.T0, w.T1, w.seed,
+                             stop_frozen=stop)
+            plan.upload()
+            out = plan.alloc_outputs()
+            row["stop" if stop else "all_sweeps"] = _time_ms(lambda: plan.anneal(out=out), 3)
+            outs[stop] = [getattr(out, f).cpu().numpy() for f in ("final_states", "best_E", "best_sweep",
+                                                                 "accepts", "draws", "inst_best_E")]
+        row["identical_outputs"] = all(np.array_equal(x, y) for x, y in zip(outs[False], outs[True]))
+        row["value"] = row["stop"]
+        print(json.dumps(row), flush=True)
     # warm-start network: 32 fields of 10x10 (about 85 free cells each)
     from paper_2608_25376_amd import warmstart
     grids = inputs.batch(32, seed=1, side=10, density_hi=0.2, first_id=10000)

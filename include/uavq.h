@@ -143,6 +143,12 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
                                       the same; needs a non-default stream */
 #define UAVQ_VARIANT_NOPRODUCER 0x80u /* m <= 64 at one wave per SIMD: no cut-producing wave beside
                                       each replica's wave (a schedule choice; same results) */
+#define UAVQ_STOP_FROZEN 0x100u    /* factored kernels: a replica whose sweep had neither an accept nor
+                                      a draw sweeps no more.  Every later sweep would leave it unchanged
+                                      (all its dE are at or above the draw cutoff, which never grows
+                                      along the schedule: plan_create checks, EINVAL otherwise), so
+                                      every output is the same; the launch ends when all are frozen.
+                                      Not for throughput measurements: frozen sweeps are not evaluated. */
 
 /* Launch shape chosen by uavq_autotune (never changes results). */
 typedef struct {

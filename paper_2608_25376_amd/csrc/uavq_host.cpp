@@ -345,6 +345,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     if (p->tune) pl->variant = p->tune->variant_flags & UAVQ_VARIANT_ROWMASK;
     pl->no_producer = (p->flags & UAVQ_VARIANT_NOPRODUCER) ? 1 : 0;
     if (p->tune) pl->no_producer = (p->tune->variant_flags & UAVQ_VARIANT_NOPRODUCER) ? 1 : 0;
+    pl->stop_frozen = (p->flags & UAVQ_STOP_FROZEN) ? 1 : 0;
     pl->persistent = (p->flags & UAVQ_PERSISTENT) ? 1 : 0;
     pl->graph = (p->flags & UAVQ_GRAPH) ? 1 : 0;
     const int32_t S = p->sweeps, R = p->replicas;
@@ -362,6 +363,12 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         while (d < Dmax && thr[(size_t)s * (Dmax + 1) + d] != 0) d++;
         dcut[s] = d;
     }
+    // a frozen replica stays frozen only if no later row accepts where this one rejects
+    for (int32_t s = 1; pl->stop_frozen && s < S; s++)
+        if (dcut[s] > dcut[s - 1]) {
+            delete pl;
+            return set_error(UAVQ_EINVAL, "plan_create: UAVQ_STOP_FROZEN needs a draw cutoff that never grows");
+        }
 
     // replica and state layout, per-instance descriptors
     pl->rep_offset.assign(n_inst + 1, 0);

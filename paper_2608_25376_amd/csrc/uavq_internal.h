@@ -115,6 +115,7 @@ struct uavq_plan {
     int32_t ylds_w1 = 0;         // the m <= 64 sweep runs at one wave per SIMD (launch fits the chip)
     int32_t ylds_pc = 0;         // ... with a cut-producing wave beside each replica's wave
     int32_t no_producer = 0;     // UAVQ_VARIANT_NOPRODUCER
+    int32_t stop_frozen = 0;     // UAVQ_STOP_FROZEN
     size_t queue_off = 0;                 // workspace: item counters (persistent mode)
     void *graph_exec = nullptr;           // cached hipGraphExec_t (graph mode)
     uint64_t graph_key = 0;

@@ -207,7 +207,9 @@ struct Prefetch {
     static constexpr int K = NJ == 1 ? 6 : (NJ == 2 ? 4 : 2);
 };
 
-template <int NJ>
+// STOP: built with UAVQ_STOP_FROZEN (a replica whose sweep had neither an
+// accept nor a draw sweeps no more; the block leaves when all have stopped).
+template <int NJ, bool STOP>
 __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *smem) {
     using Ops = RowOps<NJ>;
     constexpr int KP = Prefetch<NJ>::K;
@@ -223,6 +225,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     uint8_t *sD = smem + 4 * (size_t)Ts;
     uint8_t *sdep = sD + al16((size_t)m * m);
     __shared__ int s_first_sh;
+    __shared__ int s_live[2];   // replicas of the block that can still change, by sweep parity
 
     {
         const uint4 *gD = reinterpret_cast<const uint4 *>(a.ws + d.d_off);
@@ -236,7 +239,10 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     const int r = it.rep0 + wave;
     const int64_t grep = d.rep_base + r;
     const int s0 = active ? max(a.start_sweep ? a.start_sweep[grep] : 0, a.s_begin) : a.s_end;
-    if (threadIdx.x == 0) s_first_sh = a.s_end;
+    if (threadIdx.x == 0) {
+        s_first_sh = a.s_end;
+        if (STOP) s_live[0] = s_live[1] = 0;
+    }
     __syncthreads();
     if (L == 0) atomicMin(&s_first_sh, s0);
     __syncthreads();
@@ -315,6 +321,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     }
     int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
     uint32_t ndraw_lane = 0;   // draws of the lane's sites
+    bool frozen = false;       // stop_frozen: a sweep had neither an accept nor a draw
     int dep[NJ];   // start-cell costs of this lane's cells (the fixed rows 0 and m+1)
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
@@ -337,7 +344,9 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         const int dcut = uniform_load(a.dcut, s);
         const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
-        if (active && s >= s0) {
+        if (STOP && threadIdx.x == 0) s_live[(s + 1) & 1] = 0;   // its last reader passed the previous sweep's barriers
+        if (active && s >= s0 && !frozen) {
+            const uint32_t ndl0 = STOP ? ndraw_lane : 0u;
             // Yp = Y_{t-1} (final), Yc = Y_t (updated on flips), Yn = Y_{t+1}, Ynn = Y_{t+2}
             int Yp[NJ], Yc[NJ], Yn[NJ], Ynn[NJ];
             uint32_t mc[2 * NJ], mn[2 * NJ], mnn[2 * NJ];
@@ -518,6 +527,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
                     }
                 }
             nacc += nacc_s;
+            if (STOP && nacc_s == 0 && !ballot64(ndraw_lane != ndl0)) frozen = true;
             if (nacc_s) {
                 E += wave_sum64((int64_t)Elane);
                 Elane = 0;
@@ -536,9 +546,12 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
                 }
             }
         }
+        // replicas that can still change: active and not frozen, or not started yet
+        if (STOP && L == 0 && active && !frozen) atomicAdd(&s_live[s & 1], 1);
         // one table row in LDS: every wave is done with row s before row s + 1
         // (prefetched into registers during the sweep) replaces it
         __syncthreads();
+        const bool all_frozen = STOP && s_live[s & 1] == 0;
         if (has_next) {
             uint4 *dst = reinterpret_cast<uint4 *>(sthr);
 #pragma unroll
@@ -549,6 +562,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
             for (int i = threadIdx.x + KP * nthr; i < n4_next; i += nthr) dst[i] = src_next[i];
         }
         __syncthreads();
+        if (all_frozen) break;   // the same for every wave of the block
     }
 
     if (active) {
@@ -587,26 +601,27 @@ __device__ __forceinline__ int next_item(const KArgs &a, int iter) {
     return k < a.queue_n ? a.item_base + k : -1;
 }
 
-template <int NJ>
+template <int NJ, bool STOP>
 __global__ __launch_bounds__(1024) void k_sweep_factored(KArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     for (int iter = 0;; iter++) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
-        factored_item<NJ>(a, itx, smem);
+        factored_item<NJ, STOP>(a, itx, smem);
     }
 }
 
 // The fourth chunk class (m <= 256) holds more state per lane than a
 // 1024-thread block's register budget allows: built for at most
 // kWideMaxWaves waves per block and two waves per SIMD.
+template <bool STOP>
 __global__ __launch_bounds__(64 * kWideMaxWaves) __attribute__((amdgpu_waves_per_eu(1, 2))) void k_sweep_factored4(
     KArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     for (int iter = 0;; iter++) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
-        factored_item<4>(a, itx, smem);
+        factored_item<4, STOP>(a, itx, smem);
     }
 }
 
@@ -628,7 +643,7 @@ __global__ __launch_bounds__(64 * kWideMaxWaves) __attribute__((amdgpu_waves_per
 // walk leaves idle.  The producer works for sweep s+1 only if sweep s-1 had a
 // draw; without cuts the consumer draws for itself, reading the table row from
 // global memory (the LDS row is the producer's).
-template <bool PC>
+template <bool PC, bool STOP>
 __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem) {
     constexpr int KP = 6;
     const WorkItem it = a.items[itx];
@@ -661,6 +676,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     int *pc_valid = reinterpret_cast<int *>(cutbuf + (size_t)ncons * 2 * NB * 64);
     int *pc_drew = pc_valid + 2 * ncons;
     __shared__ int s_first_sh;
+    __shared__ int s_live[2];   // replicas of the block that can still change, by sweep parity
 
     {
         const uint4 *gD = reinterpret_cast<const uint4 *>(a.ws + d.d_off);
@@ -679,7 +695,10 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     const int r = it.rep0 + slot;
     const int64_t grep = d.rep_base + r;
     const int s0 = active ? max(a.start_sweep ? a.start_sweep[grep] : 0, a.s_begin) : a.s_end;
-    if (threadIdx.x == 0) s_first_sh = a.s_end;
+    if (threadIdx.x == 0) {
+        s_first_sh = a.s_end;
+        if (STOP) s_live[0] = s_live[1] = 0;
+    }
     if (PC && producer && L < 2) {
         pc_valid[2 * slot + L] = 0;   // no cuts yet
         pc_drew[2 * slot + L] = 1;    // no history: produce
@@ -764,6 +783,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     }
     int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
     uint32_t ndraw_lane = 0;   // draws of the lane's sites visited by the sequential walk
+    bool frozen = false;       // stop_frozen: a sweep had neither an accept nor a draw
 
     for (int s = s_first; s < a.s_end; s++) {
         uint4 pre[KP];
@@ -781,6 +801,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         const int dcut = uniform_load(a.dcut, s);
         const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
+        if (STOP && threadIdx.x == 0) s_live[(s + 1) & 1] = 0;   // its last reader passed the previous sweep's barriers
         if (PC && producer) {
             // cuts of every site for sweep s+1 (table row s+1 is in LDS)
             const int sp = s + 1;
@@ -799,7 +820,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                     cb[b * 64] = make_uint2((uint32_t)c0 | ((uint32_t)c1 << 16), (uint32_t)c2 | ((uint32_t)c3 << 16));
                 }
             }
-        } else if (active && s >= s0) {
+        } else if (active && s >= s0 && !frozen) {
             // PC: cuts for this sweep from the producer, if it made them
             const bool cv = PC && pc_valid[2 * slot + (s & 1)] != 0;
             const uint2 *cbs = cutbuf + (size_t)(2 * slot + (s & 1)) * NB * 64 + L;
@@ -1002,11 +1023,10 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             }
             nacc += nacc_s;
             ndraw += ndraw_s;
-            if (PC) {
-                // tell the producer whether this sweep drew (it then makes the cuts of sweep s+2)
-                const bool drew = ndraw_s != 0 || (ballot64(ndraw_lane != ndl0) & lanes_m) != 0;
-                if (L == 0) pc_drew[2 * slot + (s & 1)] = drew ? 1 : 0;
-            }
+            const bool drew = ndraw_s != 0 || (ballot64(ndraw_lane != ndl0) & lanes_m) != 0;
+            // tell the producer whether this sweep drew (it then makes the cuts of sweep s+2)
+            if (PC && L == 0) pc_drew[2 * slot + (s & 1)] = drew ? 1 : 0;
+            if (STOP && nacc_s == 0 && !drew) frozen = true;
             if (nacc_s) {
                 E += wave_sum64((int64_t)Elane);
                 Elane = 0;
@@ -1018,9 +1038,12 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                 improved = true;
             }
         }
+        // replicas that can still change: active and not frozen, or not started yet
+        if (STOP && L == 0 && !producer && active && !frozen) atomicAdd(&s_live[s & 1], 1);
         // one table row in LDS: every wave is done with row s before row s + 1
         // (prefetched into registers during the sweep) replaces it
         __syncthreads();
+        const bool all_frozen = STOP && s_live[s & 1] == 0;
         if (has_next) {
             uint4 *dst = reinterpret_cast<uint4 *>(sthr);
 #pragma unroll
@@ -1031,6 +1054,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             for (int i = threadIdx.x + KP * nthr; i < n4_next; i += nthr) dst[i] = src_next[i];
         }
         __syncthreads();
+        if (all_frozen) break;   // the same for every wave of the block
     }
 
     if (active && !producer) {
@@ -1070,35 +1094,38 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     }
 }
 
+template <bool STOP>
 __global__ __launch_bounds__(1024) void k_sweep_ylds(KArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     for (int iter = 0;; iter++) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
-        ylds_item<false>(a, itx, smem);
+        ylds_item<false, STOP>(a, itx, smem);
     }
 }
 
 // Same sweep for launches that hold at most one wave per SIMD: each replica's
 // walk is a latency-bound chain, so with no other wave to switch to the
 // compiler may spend registers on overlapping independent work instead.
+template <bool STOP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_sweep_ylds_w1(KArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     for (int iter = 0;; iter++) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
-        ylds_item<false>(a, itx, smem);
+        ylds_item<false, STOP>(a, itx, smem);
     }
 }
 
 // The same launch shape with a cut-producing wave beside each replica's wave
 // (two waves per SIMD).
+template <bool STOP>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sweep_ylds_pc(KArgs a) {
     extern __shared__ __align__(16) uint8_t smem[];
     for (int iter = 0;; iter++) {
         const int itx = next_item(a, iter);
         if (itx < 0) break;
-        ylds_item<true>(a, itx, smem);
+        ylds_item<true, STOP>(a, itx, smem);
     }
 }
 
@@ -1184,13 +1211,19 @@ bool ylds_fits(const uavq_plan *pl) {
 
 static bool use_ylds(const uavq_plan *pl) { return pl->variant != UAVQ_VARIANT_ROWMASK && ylds_fits(pl); }
 
+template <bool STOP>
+static const void *class_kernel_t(const uavq_plan *pl, int cls) {
+    if (cls == 1 && use_ylds(pl) && pl->ylds_pc) return (const void *)k_sweep_ylds_pc<STOP>;
+    if (cls == 1 && use_ylds(pl))
+        return pl->ylds_w1 ? (const void *)k_sweep_ylds_w1<STOP> : (const void *)k_sweep_ylds<STOP>;
+    if (cls == 1) return (const void *)k_sweep_factored<1, STOP>;
+    if (cls == 2) return (const void *)k_sweep_factored<2, STOP>;
+    if (cls == 3) return (const void *)k_sweep_factored<3, STOP>;
+    return (const void *)k_sweep_factored4<STOP>;
+}
+
 static const void *class_kernel(const uavq_plan *pl, int cls) {
-    if (cls == 1 && use_ylds(pl) && pl->ylds_pc) return (const void *)k_sweep_ylds_pc;
-    if (cls == 1 && use_ylds(pl)) return pl->ylds_w1 ? (const void *)k_sweep_ylds_w1 : (const void *)k_sweep_ylds;
-    if (cls == 1) return (const void *)k_sweep_factored<1>;
-    if (cls == 2) return (const void *)k_sweep_factored<2>;
-    if (cls == 3) return (const void *)k_sweep_factored<3>;
-    return (const void *)k_sweep_factored4;
+    return pl->stop_frozen ? class_kernel_t<true>(pl, cls) : class_kernel_t<false>(pl, cls);
 }
 
 // Kernel attributes and occupancy, once per plan and outside any stream
@@ -1245,20 +1278,10 @@ static int launch_class(const uavq_plan *pl, KArgs a, int cls, hipStream_t st) {
     const bool timed = pl->timing && !pl->graph;
     if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls], st));
     const size_t lds = pl->lds_class[cls];
-    if (cls == 1 && use_ylds(pl) && pl->ylds_pc)
-        hipLaunchKernelGGL(k_sweep_ylds_pc, dim3(grid), dim3(128 * wpb), lds, st, a);
-    else if (cls == 1 && use_ylds(pl) && pl->ylds_w1)
-        hipLaunchKernelGGL(k_sweep_ylds_w1, dim3(grid), dim3(64 * wpb), lds, st, a);
-    else if (cls == 1 && use_ylds(pl))
-        hipLaunchKernelGGL(k_sweep_ylds, dim3(grid), dim3(64 * wpb), lds, st, a);
-    else if (cls == 1)
-        hipLaunchKernelGGL(k_sweep_factored<1>, dim3(grid), dim3(64 * wpb), lds, st, a);
-    else if (cls == 2)
-        hipLaunchKernelGGL(k_sweep_factored<2>, dim3(grid), dim3(64 * wpb), lds, st, a);
-    else if (cls == 3)
-        hipLaunchKernelGGL(k_sweep_factored<3>, dim3(grid), dim3(64 * wpb), lds, st, a);
-    else
-        hipLaunchKernelGGL(k_sweep_factored4, dim3(grid), dim3(64 * wpb), lds, st, a);
+    const void *kern = class_kernel(pl, cls);
+    const int threads = (cls == 1 && use_ylds(pl) && pl->ylds_pc ? 128 : 64) * wpb;
+    void *kargs[] = {&a};
+    UAVQ_HIP(hipLaunchKernel(kern, dim3(grid), dim3(threads), kargs, lds, st));
     UAVQ_HIP(hipGetLastError());
     if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls + 1], st));
     return UAVQ_OK;

@@ -23,6 +23,7 @@ VARIANT_ROWMASK = 0x10
 PERSISTENT = 0x20
 GRAPH = 0x40
 VARIANT_NOPRODUCER = 0x80
+STOP_FROZEN = 0x100
 CHUNK_CLASSES = 4          # sweep kernel classes by ceil(m / 64); m <= 256
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
@@ -309,7 +310,7 @@ class Plan:
     def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
                  T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
                  rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None,
-                 no_producer: bool = False):
+                 no_producer: bool = False, stop_frozen: bool = False):
         self.qubos = list(qubos)
         n = len(self.qubos)
         arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in self.qubos])
@@ -318,6 +319,7 @@ class Plan:
         flags = (KERNEL_DENSE if dense else 0) | (VARIANT_ROWMASK if rowmask else 0)
         flags |= (PERSISTENT if persistent else 0) | (GRAPH if graph else 0)
         flags |= VARIANT_NOPRODUCER if no_producer else 0
+        flags |= STOP_FROZEN if stop_frozen else 0
         self._tune = tune
         p = _Params(replicas, sweeps, T0, T1, seed, flags, waves_per_block,
                     C.pointer(tune) if tune is not None else None)
