@@ -186,3 +186,25 @@ def test_time_limited_mode(U, oracle_lib):
     dmax, thr = oracle_lib.thresholds(100.0, 0.5, S)
     orc = oracle_lib.anneal(o, done, 100.0, 0.5, 1, g.inst_id, reps, table=(dmax, thr[:done].copy()), threads=3)
     compare_replicas(gi, orc, reps, "time-limited prefix")
+
+
+def test_energy_check_flags_a_corrupted_state(U):
+    """The invariant check (MFMA energy of the final states against the
+    incrementally kept energies) is sensitive: after one bit of one replica's
+    state is flipped, exactly that replica disagrees."""
+    import torch
+    g = inputs.grid(6, 6, 0.1, seed=3, inst=2)
+    R, S = 32, 50
+    say(f"case: invariant check R={R} S={S}")
+    qs, plan = _plan(U, [g], R, S, 80.0, 0.5, 3)
+    check = torch.zeros(plan.total_replicas, dtype=torch.int64, device="cuda")
+    out = _run(plan, [0, S], check_E=check)
+    final_E = out.final_E.cpu().numpy()
+    assert np.array_equal(check.cpu().numpy(), final_E)
+    q = qs[0]
+    states = out.final_states.clone()
+    states[5 * q.state_words + 2] ^= 1          # one bit of replica 5's state
+    E2 = torch.empty(R, dtype=torch.int64, device="cuda")
+    U.energy_eval_dev(q, states, E2)
+    torch.cuda.synchronize()
+    assert list(np.nonzero(E2.cpu().numpy() != final_E)[0]) == [5]
