@@ -73,6 +73,35 @@ def test_multi_chunk_rows(U, oracle_lib, side, dens, inst):
     _check_instance(U, oracle_lib, g, 9, 12, 200.0, 0.5, 3)
 
 
+@pytest.mark.parametrize("rows,cols,m", [(8, 9, 63), (8, 9, 64), (8, 9, 65), (12, 12, 127), (12, 12, 128),
+                                         (12, 12, 129), (14, 14, 191), (14, 14, 192), (14, 14, 193)])
+def test_chunk_class_boundaries(U, oracle_lib, rows, cols, m):
+    """Fields whose free-cell count sits on either side of a 64-cell chunk
+    boundary (the kernel changes there), against the oracle on two replicas
+    started from random tours over a short hot schedule."""
+    from paper_2608_25376_amd.inputs import Grid
+    rng = np.random.default_rng(m)
+    nofly = np.zeros(rows * cols, np.uint8)
+    nofly[1 + rng.choice(rows * cols - 1, rows * cols - 1 - m, replace=False)] = 1
+    g = Grid(rows, cols, nofly, inst_id=50 + m)
+    assert g.n_free == m
+    R, S, T0, T1 = 8, 4, 150.0, 50.0
+    x0 = np.zeros((R, m * m), np.uint8)
+    for r in range(R):
+        X = np.zeros((m, m), np.uint8)
+        X[np.arange(m), rng.permutation(m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = np.ones(R, np.uint8)
+    say(f"case: class boundary {rows}x{cols} m={m} R={R} S={S}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, 4, init_x=[x0], seeded=seeded, check_E=True)
+    gi = split(U, qs, plan, res)[0]
+    assert np.array_equal(gi["check_E"], gi["final_E"])
+    o = oracle_lib.OracleQubo(rows, cols, nofly=nofly, dense=m <= 80)
+    reps = [0, R - 1]
+    orc = oracle_lib.anneal(o, S, T0, T1, 4, g.inst_id, reps, init_x=x0[reps], threads=2)
+    compare_replicas(gi, orc, reps, f"m={m}")
+
+
 @pytest.mark.parametrize("side,dens,inst", [(14, 0.0, 12), (16, 0.05, 13)])
 def test_fourth_class_fields(U, oracle_lib, side, dens, inst):
     """192 < m <= 256 (up to 65,025 variables): the fourth chunk class's kernel
