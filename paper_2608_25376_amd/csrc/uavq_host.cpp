@@ -50,6 +50,21 @@ static uint32_t threshold(int32_t d, double T) {
     return v >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)v;
 }
 
+// Rows s = 0..S-1 of the acceptance table, entries 0..Dmax of each, row s at
+// dst + s * stride.  exp(-k/T) decreases in k, so past a row's first zero
+// every entry is zero and needs no exp.
+static void fill_schedule(double T0, double T1, int32_t S, int32_t Dmax, uint32_t *dst, size_t stride) {
+    for (int32_t s = 0; s < S; s++) {
+        const double T = temperature(T0, T1, S, s);
+        uint32_t *row = dst + (size_t)s * stride;
+        row[0] = 0xFFFFFFFFu;
+        int32_t k = 1;
+        for (; k <= Dmax; k++)
+            if ((row[k] = threshold(k, T)) == 0) break;
+        for (; k <= Dmax; k++) row[k] = 0;
+    }
+}
+
 }  // namespace uavq
 
 using namespace uavq;
@@ -293,15 +308,7 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
     int32_t d = 1;
     while (threshold(d, T0) != 0) d++;
     *Dmax = d;
-    if (thr) {
-        const int32_t w = d + 1;
-        for (int32_t s = 0; s < S; s++) {
-            double T = temperature(T0, T1, S, s);
-            uint32_t *row = thr + (size_t)s * w;
-            row[0] = 0xFFFFFFFFu;
-            for (int32_t k = 1; k <= d; k++) row[k] = threshold(k, T);
-        }
-    }
+    if (thr) fill_schedule(T0, T1, S, d, thr, (size_t)d + 1);
     return UAVQ_OK;
 }
 
@@ -350,17 +357,15 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     pl->graph = (p->flags & UAVQ_GRAPH) ? 1 : 0;
     const int32_t S = p->sweeps, R = p->replicas;
 
-    std::vector<uint32_t> thr((size_t)S * (Dmax + 1));
-    uavq_schedule(p->T0, p->T1, S, &Dmax, thr.data());
     // device copy with rows padded to a multiple of 4 entries (16-byte rows)
     pl->thr_stride = (Dmax + 2 + 3) & ~3;   // entries 0..Dmax, then zeros (at least one)
     std::vector<uint32_t> thr_dev((size_t)S * pl->thr_stride, 0u);
-    for (int32_t s = 0; s < S; s++)
-        std::memcpy(&thr_dev[(size_t)s * pl->thr_stride], &thr[(size_t)s * (Dmax + 1)], 4 * (size_t)(Dmax + 1));
+    fill_schedule(p->T0, p->T1, S, Dmax, thr_dev.data(), pl->thr_stride);
     std::vector<int32_t> dcut(S);
     for (int32_t s = 0; s < S; s++) {
+        const uint32_t *row = &thr_dev[(size_t)s * pl->thr_stride];
         int32_t d = 1;
-        while (d < Dmax && thr[(size_t)s * (Dmax + 1) + d] != 0) d++;
+        while (d < Dmax && row[d] != 0) d++;
         dcut[s] = d;
     }
     // a frozen replica stays frozen only if no later row accepts where this one rejects

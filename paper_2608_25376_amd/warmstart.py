@@ -233,6 +233,44 @@ def ttt(grids, net, R, ladder, T0, T1, seed, T_warm, frac=0.5, ref_sweeps=8000, 
     return report
 
 
+SEED_KEYS = ("ttt_ms", "ladder_ms_to_all_first_hits", "solved", "fraction_at_target", "mean_gap")
+
+
+def per_seed_fields(report):
+    """The per-mode figures of one seed's report that the medians are taken over."""
+    return {m: {k: v[k] for k in SEED_KEYS if k in v} for m, v in report["modes"].items()}
+
+
+def seed_medians(per_seed):
+    """Median over seeds of every figure (per budget for the per-budget ones);
+    a scalar with a missing value on some seed gets no median."""
+    seeds = list(per_seed)
+    med = {}
+    for m in per_seed[seeds[0]]:
+        med[m] = {}
+        for k in per_seed[seeds[0]][m]:
+            vals = [per_seed[sd][m].get(k) for sd in seeds]
+            if isinstance(vals[0], dict):
+                med[m][k] = {S: float(np.median([v[S] for v in vals])) for S in vals[0]}
+            elif all(v is not None for v in vals):
+                med[m][k] = float(np.median(vals))
+    return med
+
+
+def merge_reports(paths):
+    """Combine the per-seed figures of several reports (one per set of seeds)."""
+    reps = [json.load(open(p)) for p in paths]
+    per = {}
+    for r in reps:
+        per.update(r["per_seed"])
+    out = dict(reps[0])
+    out["seeds"] = sorted(int(k) for k in per)
+    out["per_seed"] = {str(k): per[str(k)] for k in out["seeds"]}
+    out["median"] = seed_medians(out["per_seed"])
+    out["merged_from"] = [os.path.basename(p) for p in paths]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-n", type=int, default=2000)
@@ -247,16 +285,34 @@ def main():
     ap.add_argument("--ref-sweeps", type=int, default=8000)
     ap.add_argument("--T-warm", type=float, default=0.0, help="0 = choose on training instances")
     ap.add_argument("--no-single", action="store_true")
+    ap.add_argument("--seeds", default="1", help="annealing seeds of the held-out evaluation (medians reported)")
+    ap.add_argument("--params", default="", help="network parameters saved by an earlier run (.npy): "
+                    "skip labelling and training")
+    ap.add_argument("--merge", default="", help="comma-separated reports of earlier runs: combine their seeds "
+                    "and write the medians to --out (no GPU work)")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
+    if args.merge:
+        txt = json.dumps(merge_reports(args.merge.split(",")))
+        print(txt, flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(txt + "\n")
+        return
     import torch
     assert torch.cuda.is_available()
-    log = lambda s: print(s, flush=True)
+    t_start = time.perf_counter()
+    log = lambda s: print(f"[{time.perf_counter() - t_start:7.1f} s] {s}", flush=True)
     T0, T1, seed = 200.0, 0.5, 1
-    train_grids = make_instances(args.train_n, 10000)
-    data, label_ms = label_data(train_grids, args.label_replicas, args.label_sweeps, T0, T1, seed, log=log)
-    log(f"labelled {len(data)}/{len(train_grids)} training instances in {label_ms / 1e3:.1f} s")
-    net, curve, train_s = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
+    if args.params:
+        net = uavq.Mlp(np.load(args.params).astype(np.float32))
+        data, label_ms, curve, train_s = None, None, None, None
+        log(f"network loaded from {args.params}")
+    else:
+        train_grids = make_instances(args.train_n, 10000)
+        data, label_ms = label_data(train_grids, args.label_replicas, args.label_sweeps, T0, T1, seed, log=log)
+        log(f"labelled {len(data)}/{len(train_grids)} training instances in {label_ms / 1e3:.1f} s")
+        net, curve, train_s = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     ladder = [int(v) for v in args.ladder.split(",")]
     T_warm = args.T_warm
     if T_warm <= 0:
@@ -272,17 +328,29 @@ def main():
                 best = (g, cand)
         T_warm = best[1]
     held = make_instances(args.heldout_n, 20000)
-    rep = ttt(held, net, args.replicas, ladder, T0, T1, seed, T_warm, ref_sweeps=args.ref_sweeps,
-              single=not args.no_single, log=log)
-    rep.update({"train_instances": len(data), "label_replicas": args.label_replicas,
-                "label_sweeps": args.label_sweeps, "label_s": label_ms / 1e3, "train_s": train_s,
-                "train_curve": curve, "epochs": args.epochs})
+    seeds = [int(v) for v in args.seeds.split(",")]
+    reps = {}
+    for sd in seeds:
+        log(f"held-out evaluation, seed {sd}")
+        reps[sd] = ttt(held, net, args.replicas, ladder, T0, T1, sd, T_warm, ref_sweeps=args.ref_sweeps,
+                       single=not args.no_single, log=log)
+    rep = dict(reps[seeds[0]])
+    rep["seeds"] = seeds
+    rep["per_seed"] = {str(sd): per_seed_fields(r) for sd, r in reps.items()}
+    rep["median"] = seed_medians(rep["per_seed"])
+    if args.params:
+        rep.update({"params": os.path.basename(args.params)})
+    else:
+        rep.update({"train_instances": len(data), "label_replicas": args.label_replicas,
+                    "label_sweeps": args.label_sweeps, "label_s": label_ms / 1e3, "train_s": train_s,
+                    "train_curve": curve, "epochs": args.epochs})
     txt = json.dumps(rep)
     print(txt, flush=True)
     if args.out:
         with open(args.out, "w") as f:
             f.write(txt + "\n")
-        np.save(os.path.splitext(args.out)[0] + "_params.npy", net.params.cpu().numpy())
+        if not args.params:
+            np.save(os.path.splitext(args.out)[0] + "_params.npy", net.params.cpu().numpy())
 
 
 if __name__ == "__main__":
