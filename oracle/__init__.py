@@ -58,6 +58,15 @@ def lib():
         L.orc_tour_brute.restype = i32
         L.orc_held_karp.argtypes = [i32, P(i32), i32]
         L.orc_held_karp.restype = i64
+        L.orc_pt_temperature.argtypes = [dbl, dbl, i32, i32]
+        L.orc_pt_temperature.restype = dbl
+        L.orc_pt_dx.argtypes = [dbl, dbl, i32, i32, P(i32)]
+        L.orc_pt_dx.restype = i32
+        L.orc_pt_tables.argtypes = [dbl, dbl, i32, P(i32), i32, P(u32)]
+        L.orc_pt_word.argtypes = [u32, u32, u32, u32, i32]
+        L.orc_pt_word.restype = u32
+        L.orc_pt_exchange.argtypes = [i32, i32, i32, u32, u32, u32, P(i32), i32, P(u32), P(u8), P(i64), P(u64)]
+        L.orc_pt_exchange.restype = i32
         _lib = L
     return _lib
 
@@ -224,3 +233,80 @@ def instance_best(res, replicas):
     i = int(order[0])
     return dict(best_E=int(res["best_E"][i]), best_replica=int(reps[i]), best_sweep=int(res["best_sweep"][i]),
                 best_x=res["best_x"][i].copy())
+
+
+# --------------------------------------------------------------------------
+# Replica exchange (parallel tempering): K chains per replica index at the
+# fixed temperatures of a geometric ladder, neighbouring slots trading states
+# by the Metropolis rule on the product of their Boltzmann weights.  An
+# extension of the many-replica search of Sec. III-C; the rule and the draw
+# addressing are stated in oracle.c.
+# --------------------------------------------------------------------------
+PT_DX_CAP = 1 << 22
+
+
+def pt_ladder(T_hot, T_cold, K):
+    """(T[K], DX[K-1], xthr[K-1][stride]) of the ladder."""
+    T = np.array([lib().orc_pt_temperature(T_hot, T_cold, K, k) for k in range(K)])
+    DX = np.zeros(max(K - 1, 1), np.int32)
+    mx = lib().orc_pt_dx(T_hot, T_cold, K, PT_DX_CAP, _p(DX, C.c_int32)) if K > 1 else 1
+    if mx < 0:
+        raise ValueError("ladder needs T_cold < T_hot and exchange tables within the cap")
+    stride = mx + 1
+    xthr = np.zeros((max(K - 1, 1), stride), np.uint32)
+    if K > 1:
+        lib().orc_pt_tables(T_hot, T_cold, K, _p(DX, C.c_int32), stride, _p(xthr, C.c_uint32))
+    return T, DX[:K - 1].copy(), xthr[:K - 1].copy()
+
+
+def pt_exchange(x, E, rnd, seed, inst, DX, xthr, swaps=None):
+    """One exchange round in place.  x: uint8 [K, R, N]; E: int64 [K, R]."""
+    K, R, N = x.shape
+    assert x.flags.c_contiguous and E.flags.c_contiguous and E.shape == (K, R)
+    sw = swaps if swaps is not None else np.zeros(max(K - 1, 1), np.uint64)
+    xthr = np.ascontiguousarray(xthr, dtype=np.uint32)
+    lib().orc_pt_exchange(K, R, N, rnd, seed, inst, _p(np.ascontiguousarray(DX, np.int32), C.c_int32),
+                          xthr.shape[1] if K > 1 else 1, _p(xthr, C.c_uint32), _p(x, C.c_uint8),
+                          _p(E, C.c_int64), _p(sw, C.c_uint64))
+    return sw
+
+
+def pt_anneal(q, K, R, sweeps, T_hot, T_cold, seed, inst, interval=1, threads=0):
+    """Parallel tempering: slot k (seed + k, constant temperature T_k) sweeps
+    chains 0..R-1 like ``anneal``; after every ``interval`` sweeps, unless the
+    schedule has ended or K = 1, exchange round e = 0, 1, ... runs.  Each slot keeps its
+    own best (the strict minimum over its sweep ends) and counters."""
+    T, DX, xthr = pt_ladder(T_hot, T_cold, K)
+    N = q.N
+    reps = list(range(R))
+    x = np.zeros((K, R, N), np.uint8)
+    E = np.zeros((K, R), np.int64)
+    best_E = np.full((K, R), np.iinfo(np.int64).max, np.int64)
+    best_sweep = np.full((K, R), -1, np.int32)
+    best_x = np.zeros((K, R, N), np.uint8)
+    acc = np.zeros((K, R), np.uint64)
+    drw = np.zeros((K, R), np.uint64)
+    swaps = np.zeros(max(K - 1, 1), np.uint64)
+    tables = [thresholds(T[k], T[k], sweeps) for k in range(K)]
+    b, e = 0, 0
+    while b < sweeps:
+        end = min(b + interval, sweeps)
+        for k in range(K):
+            dmax, thr = tables[k]
+            res = anneal(q, end, T[k], T[k], (seed + k) & 0xFFFFFFFF, inst, reps,
+                         init_x=x[k] if b > 0 else None, start_sweep=b if b > 0 else None,
+                         threads=threads, table=(dmax, thr[:end].copy()))
+            x[k] = res["final_x"]
+            E[k] = res["final_E"]
+            better = res["best_E"] < best_E[k]
+            best_E[k][better] = res["best_E"][better]
+            best_sweep[k][better] = res["best_sweep"][better]
+            best_x[k][better] = res["best_x"][better]
+            acc[k] += res["accepts"]
+            drw[k] += res["draws"]
+        if end < sweeps and K > 1:
+            pt_exchange(x, E, e, seed, inst, DX, xthr, swaps)
+            e += 1
+        b = end
+    return dict(T=T, final_x=x, final_E=E, best_E=best_E, best_sweep=best_sweep, best_x=best_x, accepts=acc,
+                draws=drw, swaps=swaps[:K - 1], rounds=e)

@@ -537,3 +537,102 @@ int32_t orc_sample_seed(int32_t m, const uint16_t *q, uint32_t seed, uint32_t in
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Replica exchange (parallel tempering), an extension of the paper's many-  */
+/* replica search (Sec. III-C): the paper runs independent replicas; here K  */
+/* of them per chain index r sit at fixed temperatures and trade states.     */
+/*                                                                          */
+/* Ladder: T_k = T_hot (T_cold/T_hot)^(k/(K-1)), k = 0..K-1 (hottest first;  */
+/* K = 1 gives T_hot).  Slot k sweeps at the constant temperature T_k.       */
+/* Exchange between slots k and k+1 of chain r (states x, x', energies E,    */
+/* E'): the swap is accepted with probability                               */
+/*   min(1, exp((1/T_{k+1} - 1/T_k) (E' - E))),                              */
+/* the Metropolis rule on the product of the two Boltzmann weights.  In       */
+/* integers: with db = 1/T_{k+1} - 1/T_k (> 0) and d = E' - E, accept when    */
+/* d >= 0; otherwise with a = -d draw u and accept iff                       */
+/*   u < xthr[k][min(a, DX_k)],  xthr[k][a] = min(2^32-1, floor(2^32 e^{-a db}))*/
+/* (no draw when that entry is 0).  DX_k = least a >= 1 with a zero entry.   */
+/* u = word 0 of Philox({k, round, r, inst}, {seed, 5}).                     */
+/* Round e exchanges the pairs (k, k+1) with k = e mod 2, 4, ...             */
+/* ------------------------------------------------------------------------ */
+double orc_pt_temperature(double T_hot, double T_cold, int32_t K, int32_t k)
+{
+    if (K <= 1) return T_hot;
+    return T_hot * pow(T_cold / T_hot, (double)k / (double)(K - 1));
+}
+
+static uint32_t xthr_value(int64_t a, double db)
+{
+    double f = floor(ldexp(exp(-(double)a * db), 32));
+    if (f >= 4294967295.0) return 0xFFFFFFFFu;
+    return (uint32_t)f;
+}
+
+/* DX[k] for the K-1 pairs; returns the largest, or -1 when a pair's db is not
+ * positive or a DX exceeds cap. */
+int32_t orc_pt_dx(double T_hot, double T_cold, int32_t K, int32_t cap, int32_t *DX)
+{
+    int32_t mx = 1;
+    for (int32_t k = 0; k + 1 < K; k++) {
+        double db = 1.0 / orc_pt_temperature(T_hot, T_cold, K, k + 1) - 1.0 / orc_pt_temperature(T_hot, T_cold, K, k);
+        if (!(db > 0.0)) return -1;
+        int32_t a = 1;
+        while (xthr_value(a, db) != 0) {
+            if (++a > cap) return -1;
+        }
+        DX[k] = a;
+        if (a > mx) mx = a;
+    }
+    return mx;
+}
+
+/* xthr[k][a] for a = 0..DX[k] (row stride `stride` >= max DX + 1; entries past
+ * DX[k] are zero). */
+void orc_pt_tables(double T_hot, double T_cold, int32_t K, const int32_t *DX, int32_t stride, uint32_t *xthr)
+{
+    for (int32_t k = 0; k + 1 < K; k++) {
+        double db = 1.0 / orc_pt_temperature(T_hot, T_cold, K, k + 1) - 1.0 / orc_pt_temperature(T_hot, T_cold, K, k);
+        uint32_t *row = xthr + (int64_t)k * stride;
+        for (int32_t a = 0; a < stride; a++) row[a] = a <= DX[k] ? xthr_value(a, db) : 0u;
+    }
+}
+
+uint32_t orc_pt_word(uint32_t seed, uint32_t inst, uint32_t r, uint32_t round, int32_t k)
+{
+    uint32_t ctr[4] = { (uint32_t)k, round, r, inst }, key[2] = { seed, 5u }, out[4];
+    orc_philox4x32_10(ctr, key, out);
+    return out[0];
+}
+
+/* One exchange round over chains 0..R-1.  x: [K][R][N] bytes, E: [K][R].
+ * swaps[k] (may be NULL) counts accepted exchanges of pair k. */
+int32_t orc_pt_exchange(int32_t K, int32_t R, int32_t N, uint32_t round, uint32_t seed, uint32_t inst,
+                        const int32_t *DX, int32_t stride, const uint32_t *xthr,
+                        uint8_t *x, int64_t *E, uint64_t *swaps)
+{
+    uint8_t *tmp = (uint8_t *)malloc((size_t)(N > 0 ? N : 1));
+    for (int32_t k = (int32_t)(round & 1u); k + 1 < K; k += 2) {
+        for (int32_t r = 0; r < R; r++) {
+            int64_t *Eh = E + (int64_t)k * R + r, *Ec = E + (int64_t)(k + 1) * R + r;
+            int64_t d = *Ec - *Eh;
+            int accept;
+            if (d >= 0) {
+                accept = 1;
+            } else {
+                int64_t a = -d;
+                uint32_t th = xthr[(int64_t)k * stride + (a < DX[k] ? a : DX[k])];
+                accept = th != 0 && orc_pt_word(seed, inst, (uint32_t)r, round, k) < th;
+            }
+            if (!accept) continue;
+            uint8_t *xh = x + ((int64_t)k * R + r) * N, *xc = x + ((int64_t)(k + 1) * R + r) * N;
+            memcpy(tmp, xh, (size_t)N);
+            memcpy(xh, xc, (size_t)N);
+            memcpy(xc, tmp, (size_t)N);
+            int64_t t = *Eh; *Eh = *Ec; *Ec = t;
+            if (swaps) swaps[k]++;
+        }
+    }
+    free(tmp);
+    return 0;
+}
