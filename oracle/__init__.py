@@ -272,9 +272,10 @@ def pt_exchange(x, E, rnd, seed, inst, DX, xthr, swaps=None):
 
 
 def pt_anneal(q, K, R, sweeps, T_hot, T_cold, seed, inst, interval=1, threads=0):
-    """Parallel tempering: slot k (seed + k, constant temperature T_k) sweeps
-    chains 0..R-1 like ``anneal``; after every ``interval`` sweeps, unless the
-    schedule has ended or K = 1, exchange round e = 0, 1, ... runs.  Each slot keeps its
+    """Parallel tempering: slot k (instance id inst + k, constant temperature
+    T_k) sweeps chains 0..R-1 like ``anneal``; after every ``interval`` sweeps,
+    unless the schedule has ended or K = 1, exchange round e = 0, 1, ... runs
+    (its draws addressed by ``inst``).  Each slot keeps its
     own best (the strict minimum over its sweep ends) and counters."""
     T, DX, xthr = pt_ladder(T_hot, T_cold, K)
     N = q.N
@@ -293,7 +294,7 @@ def pt_anneal(q, K, R, sweeps, T_hot, T_cold, seed, inst, interval=1, threads=0)
         end = min(b + interval, sweeps)
         for k in range(K):
             dmax, thr = tables[k]
-            res = anneal(q, end, T[k], T[k], (seed + k) & 0xFFFFFFFF, inst, reps,
+            res = anneal(q, end, T[k], T[k], seed, (inst + k) & 0xFFFFFFFF, reps,
                          init_x=x[k] if b > 0 else None, start_sweep=b if b > 0 else None,
                          threads=threads, table=(dmax, thr[:end].copy()))
             x[k] = res["final_x"]

@@ -544,7 +544,8 @@ int32_t orc_sample_seed(int32_t m, const uint16_t *q, uint32_t seed, uint32_t in
 /* of them per chain index r sit at fixed temperatures and trade states.     */
 /*                                                                          */
 /* Ladder: T_k = T_hot (T_cold/T_hot)^(k/(K-1)), k = 0..K-1 (hottest first;  */
-/* K = 1 gives T_hot).  Slot k sweeps at the constant temperature T_k.       */
+/* K = 1 gives T_hot).  Slot k sweeps at the constant temperature T_k, its   */
+/* draws addressed by the instance id inst + k (inst: the chain set's id).   */
 /* Exchange between slots k and k+1 of chain r (states x, x', energies E,    */
 /* E'): the swap is accepted with probability                               */
 /*   min(1, exp((1/T_{k+1} - 1/T_k) (E' - E))),                              */

@@ -110,7 +110,7 @@ def test_exchange_conserves_chain_energies(oracle_lib):
 
 def test_pt_reduces_to_plain_anneal(oracle_lib):
     """K = 1, or no exchange round (interval >= sweeps): every slot is the plain
-    annealer at its constant temperature with seed + k."""
+    annealer at its constant temperature with instance id inst + k."""
     q = oracle_lib.OracleQubo(3, 3)
     R, S = 12, 40
     pt = oracle_lib.pt_anneal(q, 1, R, S, 30.0, 1.0, 5, 2, interval=7)
@@ -121,7 +121,7 @@ def test_pt_reduces_to_plain_anneal(oracle_lib):
     K = 3
     pt = oracle_lib.pt_anneal(q, K, R, S, 30.0, 1.0, 5, 2, interval=S)
     for k in range(K):
-        ref = oracle_lib.anneal(q, S, pt["T"][k], pt["T"][k], 5 + k, 2, list(range(R)))
+        ref = oracle_lib.anneal(q, S, pt["T"][k], pt["T"][k], 5, 2 + k, list(range(R)))
         for f in ("final_x", "final_E", "best_E", "best_sweep", "accepts"):
             assert np.array_equal(pt[f][k], ref[f]), (k, f)
 
