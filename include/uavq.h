@@ -167,6 +167,10 @@ typedef struct {
     int32_t waves_per_block;  /* replicas per workgroup; 0 = library choice.
                                  Never changes results. */
     const uavq_tune *tune;    /* optional per-class launch shape (overrides the two above) */
+    const double *inst_T;     /* optional per-instance schedules: 2 * n_inst values, (T0_i, T1_i)
+                                 for instance i (0 < T1_i <= T0_i); NULL = (T0, T1) for every
+                                 instance.  A constant schedule (T0_i = T1_i) holds one table row.
+                                 The slots of a tempering ladder run as one plan this way. */
 } uavq_anneal_params;
 
 typedef struct uavq_plan uavq_plan;
@@ -303,6 +307,40 @@ int uavq_quantize_marginals(const float *d_probs, const int32_t *d_m, int32_t ro
  * instance.  Synchronises the stream before returning. */
 int uavq_sample_seeds(const uavq_plan *plan, const uint16_t *d_q, const int64_t *q_row_off, const int32_t *n_seeded,
                       uint32_t *d_states, void *d_scratch, size_t scratch_bytes, void *stream);
+
+/* ------------------------------------------------------ replica exchange -- */
+/* Parallel tempering: an extension of the many-replica search of Sec. III-C
+ * (the paper runs independent replicas).  Each chain r = 0..R-1 has K slots at
+ * the fixed temperatures of a geometric ladder; slot k is instance k of one
+ * plan (the same QUBO, instance id inst_id + k, the constant schedule T_k via
+ * uavq_anneal_params.inst_T), run in segments (uavq_anneal_segment); between
+ * segments, neighbouring slots of a chain trade
+ * their states by the Metropolis rule on the product of the two Boltzmann
+ * weights: with d = E_{k+1} - E_k and db = 1/T_{k+1} - 1/T_k > 0 the swap is
+ * accepted with probability min(1, exp(db d)).
+ *
+ * Ladder (host): T[k] = T_hot (T_cold/T_hot)^(k/(K-1)), k = 0..K-1 (T_hot for
+ * K = 1).  For pair k = 0..K-2: xthr[k][a] = min(2^32-1, floor(2^32 exp(-a db)))
+ * for a = 0..DX[k], zero beyond; DX[k] = least a >= 1 with a zero entry.
+ * Pass xthr = NULL to query DX and *max_dx; then xthr holds (K-1)*stride
+ * uint32 with stride >= *max_dx + 1.  Errors: UAVQ_EINVAL unless
+ * 1 <= K <= 4096 and 0 < T_cold < T_hot (for K >= 2) are finite, or stride is
+ * too small; UAVQ_ETOOBIG if some DX exceeds 2^22 (slots too close). */
+int uavq_pt_ladder(double T_hot, double T_cold, int32_t K, double *T, int32_t *DX, int32_t *max_dx, uint32_t *xthr,
+                   int32_t stride);
+/* One exchange round (device pointers, asynchronous on stream): the pairs
+ * (k, k+1) with k = round mod 2, k + 2, ... of every chain.  A pair swaps
+ * when d >= 0; otherwise, with a = min(-d, DX[k]), when
+ * u < xthr[k][a] (no draw for a zero entry), u = word 0 of
+ * Philox({k, round, r, inst_id}, {seed, 5}).  A swap exchanges the chains'
+ * state words and energies.  d_states: [K][R][state_words] (the plan's
+ * final_states), d_E: [K][R] (its final_E), d_DX: [K-1],
+ * d_xthr: [K-1][stride]; d_swaps (NULL or [K-1] uint64) counts accepted swaps
+ * per pair.  K = 1 does nothing.  Errors: UAVQ_EINVAL for a null pointer,
+ * K outside 1..4096, R outside 1..2^20, state_words < 1 or stride < 2. */
+int uavq_pt_exchange(int32_t K, int32_t R, int32_t state_words, uint32_t round, uint32_t seed, uint32_t inst_id,
+                     const int32_t *d_DX, const uint32_t *d_xthr, int32_t stride, int32_t *d_states, int64_t *d_E,
+                     uint64_t *d_swaps, void *stream);
 
 /* Kernel timing for measurement: when enabled, uavq_anneal_batch records HIP
  * events on its stream around the sweep-kernel launches of this plan, and

@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuavq.so")
-SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_refresh.hip", "uavq_warm.hip"]
+SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_refresh.hip", "uavq_warm.hip", "uavq_pt.hip"]
 HEADERS = ["uavq_internal.h", "uavq_device.h", os.path.join("..", "..", "include", "uavq.h")]
 ARCH = os.environ.get("UAVQ_OFFLOAD_ARCH", "gfx950")
 

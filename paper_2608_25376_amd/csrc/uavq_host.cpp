@@ -312,6 +312,43 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
     return UAVQ_OK;
 }
 
+// ------------------------------------------------------- replica exchange --
+
+static uint32_t exchange_threshold(int64_t a, double db) {
+    double v = std::floor(std::ldexp(std::exp(-(double)a * db), 32));
+    return v >= 4294967295.0 ? 0xFFFFFFFFu : (uint32_t)v;
+}
+
+int uavq_pt_ladder(double T_hot, double T_cold, int32_t K, double *T, int32_t *DX, int32_t *max_dx, uint32_t *xthr,
+                   int32_t stride) {
+    if (!T || !max_dx || (K > 1 && !DX)) return set_error(UAVQ_EINVAL, "pt_ladder: null argument");
+    if (K < 1 || K > 4096) return set_error(UAVQ_EINVAL, "pt_ladder: K = %d outside 1..4096", K);
+    if (!std::isfinite(T_hot) || !(T_hot > 0.0) || T_hot > 1e7 ||
+        (K > 1 && (!std::isfinite(T_cold) || !(T_cold > 0.0) || !(T_cold < T_hot))))
+        return set_error(UAVQ_EINVAL, "pt_ladder: need 0 < T_cold < T_hot (finite)");
+    for (int32_t k = 0; k < K; k++) T[k] = temperature(T_hot, T_cold, K, k);
+    constexpr int32_t kCap = 1 << 22;
+    int32_t mx = 1;
+    for (int32_t k = 0; k + 1 < K; k++) {
+        const double db = 1.0 / T[k + 1] - 1.0 / T[k];
+        if (!(db > 0.0)) return set_error(UAVQ_ETOOBIG, "pt_ladder: slots %d and %d share a temperature", k, k + 1);
+        int32_t a = 1;
+        while (exchange_threshold(a, db) != 0)
+            if (++a > kCap) return set_error(UAVQ_ETOOBIG, "pt_ladder: exchange table of pair %d exceeds 2^22", k);
+        DX[k] = a;
+        mx = std::max(mx, a);
+    }
+    *max_dx = mx;
+    if (!xthr) return UAVQ_OK;
+    if (stride < mx + 1) return set_error(UAVQ_EINVAL, "pt_ladder: stride %d < max DX + 1 = %d", stride, mx + 1);
+    for (int32_t k = 0; k + 1 < K; k++) {
+        const double db = 1.0 / T[k + 1] - 1.0 / T[k];
+        uint32_t *row = xthr + (size_t)k * stride;
+        for (int32_t a = 0; a < stride; a++) row[a] = a <= DX[k] ? exchange_threshold(a, db) : 0u;
+    }
+    return UAVQ_OK;
+}
+
 // ------------------------------------------------------------------ plans --
 
 static int default_waves_per_block(int chunks) {
@@ -340,10 +377,21 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     int32_t Dmax = 0;
     int rc = uavq_schedule(p->T0, p->T1, p->sweeps, &Dmax, nullptr);
     if (rc) return rc;
+    // per-instance schedules; the table width covers the hottest
+    std::vector<double> sT(2 * (size_t)std::max(n_inst, 1));
+    for (int32_t i = 0; i < n_inst; i++) {
+        sT[2 * i] = p->inst_T ? p->inst_T[2 * i] : p->T0;
+        sT[2 * i + 1] = p->inst_T ? p->inst_T[2 * i + 1] : p->T1;
+        int32_t di = 0;
+        if (uavq_schedule(sT[2 * i], sT[2 * i + 1], p->sweeps, &di, nullptr))
+            return set_error(UAVQ_EINVAL, "plan_create: schedule of instance %d needs 0 < T1 <= T0 (finite)", i);
+        Dmax = std::max(Dmax, di);
+    }
 
     uavq_plan *pl = new (std::nothrow) uavq_plan();
     if (!pl) return set_error(UAVQ_ENOMEM, "plan_create: out of memory");
     pl->p = *p;
+    pl->p.inst_T = nullptr;   // the caller's array is read above only
     pl->n_inst = n_inst;
     pl->S = p->sweeps;
     pl->Dmax = Dmax;
@@ -357,23 +405,44 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     pl->graph = (p->flags & UAVQ_GRAPH) ? 1 : 0;
     const int32_t S = p->sweeps, R = p->replicas;
 
-    // device copy with rows padded to a multiple of 4 entries (16-byte rows)
+    // Distinct schedules share their rows: S rows for a cooling schedule, one
+    // row for a constant temperature.  Device copy with rows padded to a
+    // multiple of 4 entries (16-byte rows).
     pl->thr_stride = (Dmax + 2 + 3) & ~3;   // entries 0..Dmax, then zeros (at least one)
-    std::vector<uint32_t> thr_dev((size_t)S * pl->thr_stride, 0u);
-    fill_schedule(p->T0, p->T1, S, Dmax, thr_dev.data(), pl->thr_stride);
-    std::vector<int32_t> dcut(S);
-    for (int32_t s = 0; s < S; s++) {
+    pl->sched_T = sT;
+    std::vector<int32_t> sched_of(std::max(n_inst, 1), 0), sched_row, sched_rows;
+    std::vector<double> uT;
+    for (int32_t i = 0; i < n_inst; i++) {
+        size_t j = 0;
+        while (j < sched_row.size() && !(uT[2 * j] == sT[2 * i] && uT[2 * j + 1] == sT[2 * i + 1])) j++;
+        if (j == sched_row.size()) {
+            uT.push_back(sT[2 * i]);
+            uT.push_back(sT[2 * i + 1]);
+            const int32_t rows = (S == 1 || sT[2 * i] == sT[2 * i + 1]) ? 1 : S;
+            sched_row.push_back(sched_rows.empty() ? 0 : sched_row.back() + sched_rows.back());
+            sched_rows.push_back(rows);
+        }
+        sched_of[i] = (int32_t)j;
+    }
+    pl->thr_rows = sched_row.empty() ? 1 : sched_row.back() + sched_rows.back();
+    std::vector<uint32_t> thr_dev((size_t)pl->thr_rows * pl->thr_stride, 0u);
+    for (size_t j = 0; j < sched_row.size(); j++)
+        fill_schedule(uT[2 * j], uT[2 * j + 1], sched_rows[j], Dmax,
+                      thr_dev.data() + (size_t)sched_row[j] * pl->thr_stride, pl->thr_stride);
+    std::vector<int32_t> dcut(pl->thr_rows, 1);
+    for (int32_t s = 0; s < pl->thr_rows; s++) {
         const uint32_t *row = &thr_dev[(size_t)s * pl->thr_stride];
         int32_t d = 1;
         while (d < Dmax && row[d] != 0) d++;
         dcut[s] = d;
     }
     // a frozen replica stays frozen only if no later row accepts where this one rejects
-    for (int32_t s = 1; pl->stop_frozen && s < S; s++)
-        if (dcut[s] > dcut[s - 1]) {
-            delete pl;
-            return set_error(UAVQ_EINVAL, "plan_create: UAVQ_STOP_FROZEN needs a draw cutoff that never grows");
-        }
+    for (size_t j = 0; pl->stop_frozen && j < sched_row.size(); j++)
+        for (int32_t s = 1; s < sched_rows[j]; s++)
+            if (dcut[sched_row[j] + s] > dcut[sched_row[j] + s - 1]) {
+                delete pl;
+                return set_error(UAVQ_EINVAL, "plan_create: UAVQ_STOP_FROZEN needs a draw cutoff that never grows");
+            }
 
     // replica and state layout, per-instance descriptors
     pl->rep_offset.assign(n_inst + 1, 0);
@@ -449,6 +518,11 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         d.state_off = pl->state_offset[i];
         d.inst_id = inst_ids[i];
         d.chunks = (qi->m + 63) / 64;
+        const int32_t sj = sched_of[i];
+        d.sched_row = sched_row[sj];
+        d.sched_step = sched_rows[sj] > 1 ? 1 : 0;
+        d.tl2_a = (float)std::log2(sT[2 * i] * 0.69314718055994531);
+        d.tl2_b = d.sched_step ? (float)(std::log2(sT[2 * i + 1] / sT[2 * i]) / (S - 1)) : 0.0f;
     }
     pl->blob_bytes = align_up(off, 256);
     try {

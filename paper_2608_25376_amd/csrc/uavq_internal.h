@@ -32,6 +32,10 @@ struct InstDesc {
     int64_t state_off;  // word offset of replica 0's state
     uint32_t inst_id;
     int32_t chunks;     // ceil(m / 64)
+    // this instance's schedule: row s of its acceptance table is table row
+    // sched_row + s * sched_step (step 0: a constant temperature, one row)
+    int32_t sched_row, sched_step;
+    float tl2_a, tl2_b; // T_s ln 2 ~= exp2(tl2_a + tl2_b s): starting guess for acceptance cuts
 };
 
 // One workgroup's share: replicas rep0 .. rep0+nrep-1 of instance inst.
@@ -48,13 +52,12 @@ struct KArgs {
     int32_t item_base;          // first item of this launch
     int32_t *queue;             // persistent mode: item counter of this launch (NULL = one item per block)
     int32_t queue_n;            // items in this launch (persistent mode)
-    const uint32_t *thr;        // S rows of thr_stride entries (d = 0..Dmax used)
+    const uint32_t *thr;        // table rows of thr_stride entries (d = 0..Dmax used), per instance at its sched_row
     int32_t thr_stride;         // multiple of 4
-    const int32_t *dcut;        // S: least d with thr[s][d] == 0
+    const int32_t *dcut;        // per table row: least d with thr[row][d] == 0
     int32_t S, Dmax;
     int32_t s_begin, s_end;     // this launch runs sweeps s_begin .. s_end-1 of the S-sweep schedule
     int32_t resume;             // continue from the outputs of a segment that ended at s_begin
-    float tl2_a, tl2_b;         // T_s ln 2 ~= exp2(tl2_a + tl2_b s): starting guess for acceptance cuts
     uint32_t seed;
     int32_t n_inst;
     int64_t total_rep;
@@ -92,6 +95,8 @@ struct uavq_qubo {
 struct uavq_plan {
     uavq_anneal_params p;
     int32_t n_inst, S, Dmax, thr_stride;
+    int32_t thr_rows;                     // rows of the table (all instances' schedules)
+    std::vector<double> sched_T;          // per instance: T0_i, T1_i
     std::vector<uint8_t> blob;            // static data, uploaded verbatim at offset 0
     size_t thr_off, dcut_off, desc_off, items_off, inst_state_off_off;
     size_t blob_bytes;                    // aligned size of blob

@@ -219,6 +219,8 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
     const int nthr = blockDim.x;
     const int Ts = a.thr_stride;   // row stride of the acceptance table, a multiple of 4
+    // this instance's schedule: sweep s reads table row sched_row + s * sched_step
+    const int srow = d.sched_row, dstep = d.sched_step;
 
     // LDS: the acceptance-table row | D (m*m bytes) | start-cell costs (m bytes)
     uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
@@ -248,8 +250,8 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
     __syncthreads();
     const int s_first = s_first_sh;
     if (s_first < a.s_end) {
-        const int n4 = (a.dcut[s_first] + 2 + 3) >> 2;   // through index dcut + 1
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_first * Ts);
+        const int n4 = (a.dcut[srow + s_first * dstep] + 2 + 3) >> 2;   // through index dcut + 1
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)(srow + s_first * dstep) * Ts);
         uint4 *dst = reinterpret_cast<uint4 *>(sthr);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
     }
@@ -333,16 +335,16 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         // next table row: loads issued now, stored to LDS after this sweep
         uint4 pre[KP];
         const bool has_next = s + 1 < a.s_end;
-        const int n4_next = has_next ? (uniform_load(a.dcut, s + 1) + 2 + 3) >> 2 : 0;
-        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(s + 1) * Ts);
+        const int n4_next = has_next ? (uniform_load(a.dcut, srow + (s + 1) * dstep) + 2 + 3) >> 2 : 0;
+        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(srow + (s + 1) * dstep) * Ts);
 #pragma unroll
         for (int k = 0; k < KP; k++) {
             const int i = threadIdx.x + k * nthr;
             pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
         }
         const uint32_t *thr = sthr;
-        const int dcut = uniform_load(a.dcut, s);
-        const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
+        const int dcut = uniform_load(a.dcut, srow + s * dstep);
+        const float tl2 = __builtin_amdgcn_exp2f(d.tl2_a + d.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
         if (STOP && threadIdx.x == 0) s_live[(s + 1) & 1] = 0;   // its last reader passed the previous sweep's barriers
         if (active && s >= s0 && !frozen) {
@@ -656,6 +658,8 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     const int slot = producer ? wave - ncons : wave;
     const int NB = (m + 3) >> 2;                    // blocks of four steps
     const int Ts = a.thr_stride;
+    // this instance's schedule: sweep s reads table row sched_row + s * sched_step
+    const int srow = d.sched_row, dstep = d.sched_step;
 
     // LDS: the table row | D | start-cell costs | signed cost rows | per-wave travel rows
     uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
@@ -710,8 +714,8 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
     // the LDS table row: row s (row s+1, the producer's, with PC)
     const int s_row0 = PC ? s_first + 1 : s_first;
     if (s_row0 < a.s_end) {
-        const int n4 = (uniform_load(a.dcut, s_row0) + 2 + 3) >> 2;   // through index dcut + 1
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_row0 * Ts);
+        const int n4 = (uniform_load(a.dcut, srow + s_row0 * dstep) + 2 + 3) >> 2;   // through index dcut + 1
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)(srow + s_row0 * dstep) * Ts);
         uint4 *dst = reinterpret_cast<uint4 *>(sthr);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
     }
@@ -789,17 +793,17 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         uint4 pre[KP];
         const int s_pre = PC ? s + 2 : s + 1;   // the row the LDS table holds next
         const bool has_next = s_pre < a.s_end;
-        const int n4_next = has_next ? (uniform_load(a.dcut, s_pre) + 2 + 3) >> 2 : 0;
-        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)s_pre * Ts);
+        const int n4_next = has_next ? (uniform_load(a.dcut, srow + s_pre * dstep) + 2 + 3) >> 2 : 0;
+        const uint4 *src_next = reinterpret_cast<const uint4 *>(a.thr + (size_t)(srow + s_pre * dstep) * Ts);
 #pragma unroll
         for (int k = 0; k < KP; k++) {
             const int i = threadIdx.x + k * nthr;
             pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
         }
         // with PC the consumer's own draws read row s from global memory
-        const uint32_t *thr = PC ? a.thr + (size_t)s * Ts : sthr;
-        const int dcut = uniform_load(a.dcut, s);
-        const float tl2 = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)s);   // ~ T_s ln 2
+        const uint32_t *thr = PC ? a.thr + (size_t)(srow + s * dstep) * Ts : sthr;
+        const int dcut = uniform_load(a.dcut, srow + s * dstep);
+        const float tl2 = __builtin_amdgcn_exp2f(d.tl2_a + d.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
         if (STOP && threadIdx.x == 0) s_live[(s + 1) & 1] = 0;   // its last reader passed the previous sweep's barriers
         if (PC && producer) {
@@ -808,8 +812,8 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             const bool prod = active && sp < a.s_end && sp >= s0 && pc_drew[2 * slot + ((s - 1) & 1)] != 0;
             if (L == 0) pc_valid[2 * slot + (sp & 1)] = prod ? 1 : 0;
             if (prod) {
-                const int dcut_p = uniform_load(a.dcut, sp);
-                const float tl2p = __builtin_amdgcn_exp2f(a.tl2_a + a.tl2_b * (float)sp);
+                const int dcut_p = uniform_load(a.dcut, srow + sp * dstep);
+                const float tl2p = __builtin_amdgcn_exp2f(d.tl2_a + d.tl2_b * (float)sp);
                 const float e0p = 32.0f * tl2p - 0.5f, dm1p = (float)(dcut_p - 1);
                 uint2 *cb = cutbuf + (size_t)(2 * slot + (sp & 1)) * NB * 64 + L;
                 for (int b = 0; b < NB; b++) {
@@ -1417,8 +1421,6 @@ int uavq_anneal_segment(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const 
     a.resume = resume ? 1 : 0;
     a.Dmax = pl->Dmax;
     a.thr_stride = pl->thr_stride;
-    a.tl2_a = (float)std::log2((double)pl->p.T0 * 0.69314718055994531);
-    a.tl2_b = pl->S > 1 ? (float)(std::log2((double)pl->p.T1 / (double)pl->p.T0) / (pl->S - 1)) : 0.0f;
     a.seed = pl->p.seed;
     a.n_inst = pl->n_inst;
     a.total_rep = pl->total_rep;

@@ -221,6 +221,8 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
     const int wave = threadIdx.x >> 6, L = threadIdx.x & 63;
     const int nthr = blockDim.x, nw = nthr >> 6;
     const int Ts = a.thr_stride;
+    // this instance's schedule: sweep s reads table row sched_row + s * sched_step
+    const int srow = d.sched_row, dstep = d.sched_step;
     uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
     int32_t *h = reinterpret_cast<int32_t *>(smem + 8 * (size_t)Ts) + (size_t)wave * N;
     __shared__ int s_first_sh;
@@ -235,8 +237,8 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
     __syncthreads();
     const int s_first = s_first_sh;
     if (s_first < a.s_end) {
-        const int n = a.dcut[s_first];
-        for (int i = threadIdx.x; i < n; i += nthr) sthr[(s_first & 1) * Ts + i] = a.thr[(size_t)s_first * Ts + i];
+        const int n = a.dcut[srow + s_first * dstep];
+        for (int i = threadIdx.x; i < n; i += nthr) sthr[(s_first & 1) * Ts + i] = a.thr[(size_t)(srow + s_first * dstep) * Ts + i];
     }
 
     uint32_t *st = a.states + d.state_off + (int64_t)r * d.state_words;
@@ -278,7 +280,7 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
     }
     for (int s = s_first; s < a.s_end; s++) {
         const uint32_t *thr = sthr + (s & 1) * Ts;
-        const int dcut = a.dcut[s];
+        const int dcut = a.dcut[srow + s * dstep];
         if (active && s >= s0) {
             for (int i = 0; i < nwin; i++) {
                 const int k = 64 * i + L;
@@ -334,9 +336,9 @@ __global__ __launch_bounds__(1024) void k_sweep_dense(DenseArgs da) {
             }
         }
         if (s + 1 < a.s_end) {
-            const int n = a.dcut[s + 1];
+            const int n = a.dcut[srow + (s + 1) * dstep];
             uint32_t *dst = sthr + ((s + 1) & 1) * Ts;
-            const uint32_t *src = a.thr + (size_t)(s + 1) * Ts;
+            const uint32_t *src = a.thr + (size_t)(srow + (s + 1) * dstep) * Ts;
             for (int i2 = threadIdx.x; i2 < n; i2 += nthr) dst[i2] = src[i2];
         }
         __syncthreads();

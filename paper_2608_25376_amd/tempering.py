@@ -1,0 +1,122 @@
+"""Parallel tempering against the plain annealer at the same work.
+
+The paper runs many independent replicas through one geometric schedule
+(Sec. III-C, Alg. 1).  Parallel tempering spends the same replica-sweeps on K
+slots of R chains at the fixed temperatures of a ladder, neighbouring slots
+trading states between segments.  This driver runs both on the same fields
+(the paper's sizes of Sec. IV-D as open paths, and an 8x8 field with
+no-fly cells, 54 cells to visit, as a closed tour) and reports the best tour, its cost in seconds
+and the GPU time of each.
+
+Driver only: every numeric step runs in libuavq (QUBO build, sweeps,
+exchange rounds, decode).  Costs are in tenths of a second (a 5 m cell flown
+at 5 m/s takes one second, Sec. IV-C).
+"""
+import argparse
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+from paper_2608_25376_amd import inputs, uavq  # noqa: E402
+
+FIELDS = [  # name, rows, cols, no-fly density, closed
+    ("3x4", 3, 4, 0.0, False), ("4x4", 4, 4, 0.0, False), ("4x5", 4, 5, 0.0, False),
+    ("5x6", 5, 6, 0.0, False), ("6x6", 6, 6, 0.0, False), ("8x8_nofly0.1", 8, 8, 0.1, True),
+]
+
+
+def _cost(q, state_words):
+    path, cost = uavq.decode_path(q, state_words)
+    return None if path is None else cost / 10.0
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    r = fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return r, e0.elapsed_time(e1)
+
+
+def plain(q, inst, replicas, sweeps, T0, T1, seed):
+    plan = uavq.Plan([q], [inst], replicas, sweeps, T0, T1, seed)
+    plan.upload()
+    out = plan.alloc_outputs()
+    _, ms = _timed(lambda: plan.anneal(out=out))
+    best = int(out.inst_best_E.cpu()[0])
+    st = out.inst_best_state.cpu().numpy().view(np.uint32)[:q.state_words]
+    return {"best_E": best, "cost_s": _cost(q, st), "ms": ms}
+
+
+def tempering(q, inst, K, R, sweeps, T_hot, T_cold, seed, interval):
+    pt = uavq.ParallelTempering(q, inst, K, R, sweeps, T_hot, T_cold, seed=seed, interval=interval)
+    res, ms = _timed(pt.run)
+    rounds = res["rounds"]
+    bests = [int(v) for v in res["inst_best_E"].cpu().numpy()]
+    k = int(np.argmin(bests))
+    st = res["inst_best_state"][k].cpu().numpy().view(np.uint32)
+    sw = res["swaps"].cpu().numpy()
+    # attempts per pair: rounds whose parity matches the pair, times R chains
+    att = np.array([sum(1 for e in range(rounds) if e % 2 == j % 2) * R for j in range(K - 1)], np.float64)
+    return {"best_E": bests[k], "best_slot": k, "cost_s": _cost(q, st), "ms": ms, "rounds": rounds,
+            "swap_rate": [float(a) for a in np.where(att > 0, sw / np.maximum(att, 1), 0.0)],
+            "slot_best_E": bests, "T": [float(t) for t in pt.T]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--K", type=int, default=16)
+    ap.add_argument("--R", type=int, default=64, help="chains per slot (the plain run gets K*R replicas)")
+    ap.add_argument("--sweeps", type=int, default=1000)
+    ap.add_argument("--T-hot", type=float, default=100.0)
+    ap.add_argument("--T-cold", type=float, default=0.5)
+    ap.add_argument("--intervals", default="1,10")
+    ap.add_argument("--seeds", default="1,2,3,4,5", help="annealing seeds (medians reported)")
+    ap.add_argument("--fields", default="")
+    ap.add_argument("--out", default="")
+    args = ap.parse_args()
+    import torch
+    assert torch.cuda.is_available()
+    names = set(args.fields.split(",")) if args.fields else None
+    seeds = [int(v) for v in args.seeds.split(",")]
+    rows = []
+    q0 = uavq.qubo_build(3, 3)
+    tempering(q0, 0, 2, 8, 4, 10.0, 1.0, 1, 1)     # load the kernels before timing
+    for name, r, c, dens, closed in FIELDS:
+        if names and name not in names:
+            continue
+        g = inputs.grid(r, c, dens, seed=1, inst=0)
+        q = uavq.qubo_build(g.rows, g.cols, nofly=g.nofly, closed=closed)
+        res = {"field": name, "m": q.m, "closed": closed, "K": args.K, "R": args.R, "sweeps": args.sweeps,
+               "T_hot": args.T_hot, "T_cold": args.T_cold, "seeds": seeds, "per_seed": {}}
+        ivs = [int(v) for v in args.intervals.split(",")]
+        for sd in seeds:
+            one = {"plain": plain(q, g.inst_id, args.K * args.R, args.sweeps, args.T_hot, args.T_cold, sd)}
+            for iv in ivs:
+                one[f"pt_interval{iv}"] = tempering(q, g.inst_id, args.K, args.R, args.sweeps, args.T_hot,
+                                                    args.T_cold, sd, iv)
+            res["per_seed"][str(sd)] = one
+        # a feasible state's energy is its tour time in deciseconds
+        res["median"] = {mode: {"best_E": float(np.median([res["per_seed"][str(sd)][mode]["best_E"] for sd in seeds])),
+                                "ms": float(np.median([res["per_seed"][str(sd)][mode]["ms"] for sd in seeds])),
+                                "feasible": sum(res["per_seed"][str(sd)][mode]["cost_s"] is not None for sd in seeds)}
+                         for mode in res["per_seed"][str(seeds[0])]}
+        print(json.dumps(res), flush=True)
+        rows.append(res)
+    if args.out:
+        with open(args.out, "w") as f:
+            for res in rows:
+                f.write(json.dumps(res) + "\n")
+
+
+if __name__ == "__main__":
+    main()

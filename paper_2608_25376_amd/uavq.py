@@ -59,7 +59,7 @@ class Tune(C.Structure):
 class _Params(C.Structure):
     _fields_ = [("replicas", C.c_int32), ("sweeps", C.c_int32), ("T0", C.c_double), ("T1", C.c_double),
                 ("seed", C.c_uint32), ("flags", C.c_uint32), ("waves_per_block", C.c_int32),
-                ("tune", C.POINTER(Tune))]
+                ("tune", C.POINTER(Tune)), ("inst_T", C.POINTER(C.c_double))]
 
 
 class _PlanInfo(C.Structure):
@@ -86,6 +86,7 @@ EXPORTS = [
     "uavq_anneal_batch", "uavq_anneal_segment", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
     "uavq_mlp_param_count", "uavq_mlp_features", "uavq_mlp_workspace_bytes", "uavq_mlp_forward",
     "uavq_mlp_loss_grad", "uavq_mlp_adam", "uavq_quantize_marginals", "uavq_sample_seeds",
+    "uavq_pt_ladder", "uavq_pt_exchange",
 ]
 
 _lib = None
@@ -135,6 +136,10 @@ def lib():
         L.uavq_mlp_adam.argtypes = [vp, vp, vp, vp, C.c_int32, C.c_float, vp]
         L.uavq_quantize_marginals.argtypes = [vp, vp, C.c_int32, vp, vp]
         L.uavq_sample_seeds.argtypes = [vp, vp, P(C.c_int64), P(C.c_int32), vp, vp, C.c_size_t, vp]
+        L.uavq_pt_ladder.argtypes = [C.c_double, C.c_double, C.c_int32, P(C.c_double), P(C.c_int32), P(C.c_int32),
+                                     P(C.c_uint32), C.c_int32]
+        L.uavq_pt_exchange.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_uint32, C.c_uint32, vp, vp,
+                                       C.c_int32, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -310,7 +315,8 @@ class Plan:
     def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
                  T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
                  rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None,
-                 no_producer: bool = False, stop_frozen: bool = False):
+                 no_producer: bool = False, stop_frozen: bool = False, inst_T=None):
+        """``inst_T``: optional per-instance schedules, a sequence of (T0_i, T1_i)."""
         self.qubos = list(qubos)
         n = len(self.qubos)
         arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in self.qubos])
@@ -321,8 +327,14 @@ class Plan:
         flags |= VARIANT_NOPRODUCER if no_producer else 0
         flags |= STOP_FROZEN if stop_frozen else 0
         self._tune = tune
+        iT = None
+        if inst_T is not None:
+            iT = np.ascontiguousarray(inst_T, dtype=np.float64).reshape(-1)
+            if iT.size != 2 * n:
+                raise ValueError("inst_T needs (T0, T1) for every instance")
         p = _Params(replicas, sweeps, T0, T1, seed, flags, waves_per_block,
-                    C.pointer(tune) if tune is not None else None)
+                    C.pointer(tune) if tune is not None else None,
+                    _np_ptr(iT, C.c_double) if iT is not None else None)
         h = C.c_void_p()
         _check(lib().uavq_plan_create(arr, n, _np_ptr(ids, C.c_uint32), C.byref(p), C.byref(h)))
         self._h = h
@@ -540,3 +552,77 @@ def sample_seeds(plan: "Plan", q, q_row_off, n_seeded, states, stream=None):
     torch.cuda.synchronize()
     _check(lib().uavq_sample_seeds(plan._h, _dptr(q), _np_ptr(qo, C.c_int64), _np_ptr(ns, C.c_int32), _dptr(states),
                                    _dptr(scratch), scratch.numel(), _stream_handle(stream)))
+
+
+# ------------------------------------------------------- replica exchange --
+def pt_ladder(T_hot: float, T_cold: float, K: int):
+    """(T[K], DX[K-1], xthr[K-1][stride]) of the tempering ladder (uavq_pt_ladder)."""
+    T = np.zeros(K, np.float64)
+    DX = np.zeros(max(K - 1, 1), np.int32)
+    mx = C.c_int32()
+    _check(lib().uavq_pt_ladder(T_hot, T_cold, K, _np_ptr(T, C.c_double), _np_ptr(DX, C.c_int32), C.byref(mx),
+                                None, 0))
+    stride = mx.value + 1
+    xthr = np.zeros((max(K - 1, 1), stride), np.uint32)
+    _check(lib().uavq_pt_ladder(T_hot, T_cold, K, _np_ptr(T, C.c_double), _np_ptr(DX, C.c_int32), C.byref(mx),
+                                _np_ptr(xthr, C.c_uint32), stride))
+    return T, DX[:K - 1].copy(), xthr[:K - 1].copy()
+
+
+def pt_exchange(rnd: int, seed: int, inst_id: int, d_DX, d_xthr, states, E, swaps=None, stream=None):
+    """One exchange round (uavq_pt_exchange) on device tensors: states int32
+    [K, R, words], E int64 [K, R], d_DX int32 [K-1], d_xthr uint32 [K-1, stride]
+    (held as int32), swaps int64 [K-1] or None."""
+    K, R, W = states.shape
+    assert states.is_contiguous() and E.is_contiguous() and tuple(E.shape) == (K, R)
+    assert d_xthr.is_contiguous() and d_DX.numel() >= K - 1 and d_xthr.shape[0] >= K - 1
+    assert swaps is None or swaps.numel() >= K - 1
+    _check(lib().uavq_pt_exchange(K, R, W, rnd & 0xFFFFFFFF, seed & 0xFFFFFFFF, inst_id & 0xFFFFFFFF,
+                                  _dptr(d_DX), _dptr(d_xthr), int(d_xthr.shape[1]), _dptr(states), _dptr(E),
+                                  _dptr(swaps), _stream_handle(stream)))
+
+
+class ParallelTempering:
+    """Parallel tempering on one instance: K slots of R chains each, run as one
+    plan of K instances (the same QUBO, instance ids inst_id + k, the constant
+    schedule T_k each), so every segment is one launch for all slots.  The
+    slots sweep ``interval`` sweeps at a time (anneal_segment) and, between
+    segments, neighbouring slots exchange states (uavq_pt_exchange, rounds
+    0, 1, ...).  Every step runs in the library's kernels."""
+
+    def __init__(self, q: Qubo, inst_id: int, K: int, replicas: int, sweeps: int, T_hot: float, T_cold: float,
+                 seed: int = 1, interval: int = 1, **plan_kw):
+        import torch
+        if interval < 1:
+            raise ValueError("interval must be >= 1")
+        self.q, self.inst_id, self.K, self.R, self.S = q, int(inst_id), int(K), int(replicas), int(sweeps)
+        self.seed, self.interval = int(seed), int(interval)
+        self.T, DX, xthr = pt_ladder(T_hot, T_cold, K)
+        self.plan = Plan([q] * K, [(inst_id + k) & 0xFFFFFFFF for k in range(K)], replicas, sweeps, T_hot, T_hot,
+                         seed, inst_T=[(float(t), float(t)) for t in self.T], **plan_kw)
+        self.plan.upload()
+        self.d_DX = torch.from_numpy(np.ascontiguousarray(DX if K > 1 else np.zeros(1, np.int32))).cuda()
+        xt = xthr if K > 1 else np.zeros((1, 2), np.uint32)
+        self.d_xthr = torch.from_numpy(np.ascontiguousarray(xt).view(np.int32)).cuda()
+
+    def run(self, stream=None) -> dict:
+        """The whole schedule.  Returns per-slot views of the plan's outputs
+        (states and best_states [K, R, words], the others [K, R]; inst_best_*
+        [K]), the swaps per pair [K-1] and the number of exchange rounds."""
+        import torch
+        K, R, W = self.K, self.R, self.q.state_words
+        out = self.plan.alloc_outputs()
+        states, E = out.final_states.view(K, R, W), out.final_E.view(K, R)
+        swaps = torch.zeros(max(K - 1, 1), dtype=torch.int64, device="cuda")
+        b, rnd = 0, 0
+        while b < self.S:
+            end = min(b + self.interval, self.S)
+            self.plan.anneal(out=out, s_begin=b, s_end=end, resume=b > 0, stream=stream)
+            if end < self.S and K > 1:
+                pt_exchange(rnd, self.seed, self.inst_id, self.d_DX, self.d_xthr, states, E, swaps, stream=stream)
+                rnd += 1
+            b = end
+        return {"out": out, "states": states, "E": E, "best_E": out.best_E.view(K, R),
+                "best_sweep": out.best_sweep.view(K, R), "best_states": out.best_states.view(K, R, W),
+                "accepts": out.accepts.view(K, R), "draws": out.draws.view(K, R), "inst_best_E": out.inst_best_E,
+                "inst_best_state": out.inst_best_state.view(K, W), "swaps": swaps[:K - 1], "rounds": rnd}

@@ -1,6 +1,7 @@
 """CPU tests of the C ABI: the library loads, exports every declared entry
 point, and its host-side pieces (QUBO build, schedule table, energy, path
 decoding, validation) agree with the oracle.  No GPU call is made here."""
+import ctypes as C
 import os
 import re
 
@@ -184,3 +185,25 @@ def test_segment_range_validation(U):
     rc = U.lib().uavq_anneal_segment(p._h, None, 0, C.byref(init), C.byref(out), 0, 10, 1, None)
     assert rc == U.EINVAL
     assert U.lib().uavq_anneal_segment(None, None, 0, None, None, 0, 1, 0, None) == U.EINVAL
+
+
+def test_pt_ladder_equals_oracle(U, oracle_lib):
+    for T_hot, T_cold, K in [(200.0, 2.0, 8), (120.0, 3.0, 6), (50.0, 0.5, 2), (80.0, 8.0, 16), (30.0, 1.0, 1)]:
+        T1, D1, x1 = U.pt_ladder(T_hot, T_cold, K)
+        T2, D2, x2 = oracle_lib.pt_ladder(T_hot, T_cold, K)
+        assert T1.tobytes() == T2.tobytes()
+        assert D1.tobytes() == D2.tobytes()
+        assert x1.shape == x2.shape and x1.tobytes() == x2.tobytes()
+
+
+def test_pt_argument_errors(U):
+    for args in [(5.0, 5.0, 3), (5.0, 6.0, 2), (5.0, 1.0, 0), (5.0, 1.0, 4097), (float("nan"), 1.0, 2)]:
+        with pytest.raises(U.UavqError):
+            U.pt_ladder(*args)
+    L = U.lib()
+    # host-side validation returns before any device call
+    assert L.uavq_pt_exchange(0, 4, 1, 0, 1, 0, None, None, 2, None, None, None, None) == U.EINVAL
+    assert L.uavq_pt_exchange(3, 4, 1, 0, 1, 0, None, None, 2, None, None, None, None) == U.EINVAL
+    assert L.uavq_pt_exchange(3, 0, 1, 0, 1, 0, None, None, 2, None, None, None, None) == U.EINVAL
+    assert L.uavq_pt_exchange(1, 4, 1, 0, 1, 0, C.c_void_p(8), C.c_void_p(8), 2, C.c_void_p(8), C.c_void_p(8),
+                              None, None) == 0     # K = 1: nothing to exchange
