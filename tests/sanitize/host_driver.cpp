@@ -1,5 +1,6 @@
 // Drives the host half of libuavq (QUBO build, costs, export, host energy,
-// decode, features, schedule, plan layout and their error paths) for a build
+// decode, features, schedule, plan layout, per-instance schedules, the
+// tempering ladder and their error paths) for a build
 // under AddressSanitizer and UndefinedBehaviorSanitizer.  No device call is
 // made; the one device-side symbol the host half references is stubbed.
 #include <cstdint>
@@ -134,6 +135,44 @@ int main() {
         CHECK(ro.back() == pi.total_replicas && so.back() == pi.total_state_words);
         uavq_plan_free(pl);
     }
+    // per-instance schedules: cooling, constant and repeated ones share rows
+    {
+        std::vector<double> iT(2 * qs.size());
+        for (size_t i = 0; i < qs.size(); i++) {
+            iT[2 * i] = (i % 3 == 0) ? 80.0 : (i % 3 == 1 ? 25.0 : 120.0);
+            iT[2 * i + 1] = (i % 3 == 1) ? 25.0 : 0.5;
+        }
+        p.waves_per_block = 0;
+        p.inst_T = iT.data();
+        for (uint32_t fl : {0u, (uint32_t)UAVQ_STOP_FROZEN}) {
+            p.flags = fl;
+            uavq_plan *pl = nullptr;
+            CHECK(uavq_plan_create(qs.data(), (int32_t)qs.size(), ids.data(), &p, &pl) == UAVQ_OK && pl);
+            uavq_plan_info_t pi{};
+            CHECK(uavq_plan_info(pl, &pi) == UAVQ_OK && pi.Dmax > 0);
+            uavq_plan_free(pl);
+        }
+        p.flags = 0;
+        iT[1] = 90.0;   // T1 > T0
+        uavq_plan *pl = nullptr;
+        CHECK(uavq_plan_create(qs.data(), (int32_t)qs.size(), ids.data(), &p, &pl) == UAVQ_EINVAL && !pl);
+        p.inst_T = nullptr;
+    }
+
+    // tempering ladder: query, fill, errors
+    {
+        const int K = 9;
+        double T[K];
+        int32_t DX[K], mx = 0;
+        CHECK(uavq_pt_ladder(150.0, 1.0, K, T, DX, &mx, nullptr, 0) == UAVQ_OK && mx > 1);
+        std::vector<uint32_t> xt((size_t)(K - 1) * (mx + 1));
+        CHECK(uavq_pt_ladder(150.0, 1.0, K, T, DX, &mx, xt.data(), mx + 1) == UAVQ_OK);
+        CHECK(uavq_pt_ladder(150.0, 1.0, K, T, DX, &mx, xt.data(), mx) == UAVQ_EINVAL);
+        CHECK(uavq_pt_ladder(150.0, 150.0, K, T, DX, &mx, nullptr, 0) == UAVQ_EINVAL);
+        CHECK(uavq_pt_ladder(150.0, 1.0, 0, T, DX, &mx, nullptr, 0) == UAVQ_EINVAL);
+        CHECK(uavq_pt_ladder(150.0, 1.0, 1, T, nullptr, &mx, nullptr, 0) == UAVQ_OK && T[0] == 150.0);
+    }
+
     uavq_plan *pl = nullptr;
     p.replicas = 0;
     CHECK(uavq_plan_create(qs.data(), (int32_t)qs.size(), ids.data(), &p, &pl) == UAVQ_EINVAL && !pl);

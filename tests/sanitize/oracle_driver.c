@@ -1,5 +1,6 @@
 /* Drives the oracle (instance, costs, QUBO, energies, schedule, annealing with
- * and without a stored J, enumeration, brute force, Held-Karp, seed sampling)
+ * and without a stored J, enumeration, brute force, Held-Karp, seed sampling,
+ * replica exchange)
  * for a build under AddressSanitizer and UndefinedBehaviorSanitizer. */
 #include <stdint.h>
 #include <stdio.h>
@@ -24,6 +25,11 @@ int32_t orc_enum_min(int32_t m, const int32_t *J, const int32_t *b, int64_t c0, 
 int32_t orc_tour_brute(int32_t m, const int32_t *W, int32_t closed, int64_t *best, int64_t *n_opt);
 int64_t orc_held_karp(int32_t m, const int32_t *W, int32_t closed);
 int32_t orc_sample_seed(int32_t m, const uint16_t *q, uint32_t seed, uint32_t inst, uint32_t r, uint8_t *x);
+int32_t orc_pt_dx(double T_hot, double T_cold, int32_t K, int32_t cap, int32_t *DX);
+void orc_pt_tables(double T_hot, double T_cold, int32_t K, const int32_t *DX, int32_t stride, uint32_t *xthr);
+int32_t orc_pt_exchange(int32_t K, int32_t R, int32_t N, uint32_t round, uint32_t seed, uint32_t inst,
+                        const int32_t *DX, int32_t stride, const uint32_t *xthr, uint8_t *x, int64_t *E,
+                        uint64_t *swaps);
 
 #define CHECK(c)                                                                \
     do {                                                                        \
@@ -96,6 +102,22 @@ int main(void)
         int64_t c0 = 0, mn = 0, nmin = 0, minf = 0;
         orc_build_qubo(m, W, 2 * wmax, 1, J, b, &c0);
         CHECK(orc_enum_min(m, J, b, c0, &mn, &nmin, arg, &minf) == 0 && mn < minf);
+    }
+    /* replica exchange: ladder tables and a few rounds */
+    {
+        enum { K = 6, R = 7, N = 5 };
+        int32_t DX[K];
+        int32_t mx = orc_pt_dx(90.0, 2.0, K, 1 << 22, DX);
+        CHECK(mx > 1);
+        uint32_t *xt = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(K - 1) * (size_t)(mx + 1));
+        orc_pt_tables(90.0, 2.0, K, DX, mx + 1, xt);
+        uint8_t x[K * R * N];
+        int64_t E[K * R];
+        uint64_t sw[K - 1] = {0};
+        for (int i = 0; i < K * R * N; i++) x[i] = (uint8_t)(i & 1);
+        for (int i = 0; i < K * R; i++) E[i] = (int64_t)((i * 37) % 101) - 20;
+        for (uint32_t rnd = 0; rnd < 5; rnd++) CHECK(orc_pt_exchange(K, R, N, rnd, 3, 1, DX, mx + 1, xt, x, E, sw) == 0);
+        free(xt);
     }
     printf("oracle driver: clean\n");
     return 0;
