@@ -313,7 +313,8 @@ int uavq_sample_seeds(const uavq_plan *plan, const uint16_t *d_q, const int64_t 
  * (the paper runs independent replicas).  Each chain r = 0..R-1 has K slots at
  * the fixed temperatures of a geometric ladder; slot k is instance k of one
  * plan (the same QUBO, instance id inst_id + k, the constant schedule T_k via
- * uavq_anneal_params.inst_T), run in segments (uavq_anneal_segment); between
+ * uavq_anneal_params.inst_T; chain sets that must be independent need
+ * disjoint id ranges), run in segments (uavq_anneal_segment); between
  * segments, neighbouring slots of a chain trade
  * their states by the Metropolis rule on the product of the two Boltzmann
  * weights: with d = E_{k+1} - E_k and db = 1/T_{k+1} - 1/T_k > 0 the swap is

@@ -588,7 +588,9 @@ class ParallelTempering:
     schedule T_k each), so every segment is one launch for all slots.  The
     slots sweep ``interval`` sweeps at a time (anneal_segment) and, between
     segments, neighbouring slots exchange states (uavq_pt_exchange, rounds
-    0, 1, ...).  Every step runs in the library's kernels."""
+    0, 1, ...).  Every step runs in the library's kernels.  The slots' draws
+    are addressed by the ids inst_id .. inst_id + K - 1: give chain sets that
+    must be independent disjoint id ranges."""
 
     def __init__(self, q: Qubo, inst_id: int, K: int, replicas: int, sweeps: int, T_hot: float, T_cold: float,
                  seed: int = 1, interval: int = 1, **plan_kw):
