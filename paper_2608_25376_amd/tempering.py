@@ -4,9 +4,10 @@ The paper runs many independent replicas through one geometric schedule
 (Sec. III-C, Alg. 1).  Parallel tempering spends the same replica-sweeps on K
 slots of R chains at the fixed temperatures of a ladder, neighbouring slots
 trading states between segments.  This driver runs both on the same fields
-(the paper's sizes of Sec. IV-D as open paths, and an 8x8 field with
-no-fly cells, 54 cells to visit, as a closed tour) and reports the best tour, its cost in seconds
-and the GPU time of each.
+(the paper's sizes of Sec. IV-D as open paths, and an 8x8 field with no-fly
+cells, 54 cells to visit, as a closed tour), and the plain annealer once more
+with several times the sweeps for a comparison at about equal GPU time; it
+reports the best tour, its cost in seconds and the GPU time of each.
 
 Driver only: every numeric step runs in libuavq (QUBO build, sweeps,
 exchange rounds, decode).  Costs are in tenths of a second (a 5 m cell flown
@@ -81,6 +82,9 @@ def main():
     ap.add_argument("--T-cold", type=float, default=0.5)
     ap.add_argument("--intervals", default="1,10")
     ap.add_argument("--seeds", default="1,2,3,4,5", help="annealing seeds (medians reported)")
+    ap.add_argument("--long-factor", type=int, default=3,
+                    help="also run the plain annealer with this many times the sweeps (about the GPU time of "
+                         "tempering with an exchange every 10 sweeps); 0 = skip")
     ap.add_argument("--fields", default="")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
@@ -101,6 +105,9 @@ def main():
         ivs = [int(v) for v in args.intervals.split(",")]
         for sd in seeds:
             one = {"plain": plain(q, g.inst_id, args.K * args.R, args.sweeps, args.T_hot, args.T_cold, sd)}
+            if args.long_factor > 0:
+                one[f"plain_x{args.long_factor}"] = plain(q, g.inst_id, args.K * args.R, args.long_factor * args.sweeps,
+                                                          args.T_hot, args.T_cold, sd)
             for iv in ivs:
                 one[f"pt_interval{iv}"] = tempering(q, g.inst_id, args.K, args.R, args.sweeps, args.T_hot,
                                                     args.T_cold, sd, iv)
