@@ -207,3 +207,27 @@ def test_pt_argument_errors(U):
     assert L.uavq_pt_exchange(3, 0, 1, 0, 1, 0, None, None, 2, None, None, None, None) == U.EINVAL
     assert L.uavq_pt_exchange(1, 4, 1, 0, 1, 0, C.c_void_p(8), C.c_void_p(8), 2, C.c_void_p(8), C.c_void_p(8),
                               None, None) == 0     # K = 1: nothing to exchange
+
+
+def test_plan_instance_schedules_host(U):
+    """Per-instance schedules (host side): the table width covers the hottest
+    instance, a constant schedule stores one row, identical schedules share
+    their rows, and invalid ones are rejected."""
+    q = U.qubo_build(5, 5)
+    S, R = 400, 8
+    cool = U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1)
+    const = U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1, inst_T=[(50.0, 50.0), (20.0, 20.0)])
+    shared = U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1, inst_T=[(50.0, 0.5), (50.0, 0.5)])
+    mixed = U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1, inst_T=[(50.0, 0.5), (90.0, 0.5)])
+    d90 = U.schedule(90.0, 0.5, S, table=False)[0]
+    assert cool.Dmax == const.Dmax == shared.Dmax == U.schedule(50.0, 0.5, S, table=False)[0]
+    assert mixed.Dmax == d90
+    # two constant rows against S rows: the workspace shrinks by about S-2 table rows
+    assert const.ws_bytes < cool.ws_bytes - (S - 4) * 4 * cool.Dmax
+    assert shared.ws_bytes == cool.ws_bytes
+    assert mixed.ws_bytes > cool.ws_bytes + (S - 4) * 4 * cool.Dmax
+    for bad in ([(50.0, 60.0), (50.0, 0.5)], [(0.0, 0.0), (50.0, 0.5)], [(50.0, 0.5)]):
+        with pytest.raises((U.UavqError, ValueError)):
+            U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1, inst_T=bad)
+    # a constant schedule never grows its cutoff, so it is allowed with UAVQ_STOP_FROZEN
+    U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1, inst_T=[(50.0, 0.5), (5.0, 5.0)], stop_frozen=True)
