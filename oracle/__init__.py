@@ -67,6 +67,10 @@ def lib():
         L.orc_pt_word.restype = u32
         L.orc_pt_exchange.argtypes = [i32, i32, i32, u32, u32, u32, P(i32), i32, P(u32), P(u8), P(i64), P(u64)]
         L.orc_pt_exchange.restype = i32
+        L.orc_pt_anneal.argtypes = [i32, P(i32), P(i32), i32, P(i32), i64, i32, i32, i32, i32, P(u32), P(i32), i32,
+                                    P(u32), u32, u32, i32, P(i32), P(u8), P(i64), P(i64), P(i32), P(u8), P(u64),
+                                    P(u64), P(u64), i32]
+        L.orc_pt_anneal.restype = i32
         _lib = L
     return _lib
 
@@ -311,3 +315,35 @@ def pt_anneal(q, K, R, sweeps, T_hot, T_cold, seed, inst, interval=1, threads=0)
         b = end
     return dict(T=T, final_x=x, final_E=E, best_E=best_E, best_sweep=best_sweep, best_x=best_x, accepts=acc,
                 draws=drw, swaps=swaps[:K - 1], rounds=e)
+
+
+def pt_anneal_chains(q, K, chains, sweeps, T_hot, T_cold, seed, inst, interval=1, threads=0):
+    """The tempering of ``pt_anneal`` for the listed chain ids only, as one C
+    loop per chain that keeps its fields across exchange rounds (chains are
+    independent, so any subset gives those chains' outputs).  Arrays are
+    indexed [chain index, slot]; swaps per chain and pair."""
+    T, DX, xthr = pt_ladder(T_hot, T_cold, K)
+    rows = [thresholds(T[k], T[k], 1) for k in range(K)]
+    dmax = max(d for d, _ in rows)
+    thr = np.zeros((K, dmax + 1), np.uint32)
+    for k, (d, t) in enumerate(rows):
+        thr[k, :d + 1] = t[0]
+    ch = np.ascontiguousarray(chains, dtype=np.int32)
+    n, N = ch.size, q.N
+    out = dict(final_x=np.zeros((n, K, N), np.uint8), final_E=np.zeros((n, K), np.int64),
+               best_E=np.zeros((n, K), np.int64), best_sweep=np.zeros((n, K), np.int32),
+               best_x=np.zeros((n, K, N), np.uint8), accepts=np.zeros((n, K), np.uint64),
+               draws=np.zeros((n, K), np.uint64), swaps=np.zeros((n, max(K - 1, 1)), np.uint64))
+    DXa = np.ascontiguousarray(DX if K > 1 else np.zeros(1, np.int32), dtype=np.int32)
+    xt = np.ascontiguousarray(xthr if K > 1 else np.zeros((1, 2), np.uint32), dtype=np.uint32)
+    rc = lib().orc_pt_anneal(q.m, _p(q.J, C.c_int32), _p(q.W, C.c_int32), q.P, _p(q.b, C.c_int32), q.c0, K, sweeps,
+                             interval, dmax, _p(thr, C.c_uint32), _p(DXa, C.c_int32), xt.shape[1], _p(xt, C.c_uint32),
+                             seed, inst, n, _p(ch, C.c_int32), _p(out["final_x"], C.c_uint8),
+                             _p(out["final_E"], C.c_int64), _p(out["best_E"], C.c_int64),
+                             _p(out["best_sweep"], C.c_int32), _p(out["best_x"], C.c_uint8),
+                             _p(out["accepts"], C.c_uint64), _p(out["draws"], C.c_uint64),
+                             _p(out["swaps"], C.c_uint64), threads)
+    assert rc == 0
+    out["swaps"] = out["swaps"][:, :K - 1]
+    out["T"] = T
+    return out

@@ -310,6 +310,39 @@ static int64_t field_energy_mismatch(int32_t m, const int32_t *J, const int32_t 
     return bad;
 }
 
+/* One in-order sweep s of replica r over all N sites with table row `row`
+ * (the loop body of the annealer above); updates x, h, E and the counters. */
+static void sweep_once(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const uint32_t *row, int32_t Dmax,
+                       uint32_t seed, uint32_t inst, uint32_t r, int32_t s, uint8_t *x, int32_t *h, int64_t *E,
+                       uint64_t *acc, uint64_t *drw)
+{
+    int32_t N = m * m;
+    for (int32_t k = 0; k < N; k++) {
+        int32_t t = k / m + 1, c = k % m;
+        int32_t dE = x[k] ? -h[k] : h[k];
+        int accept;
+        if (dE <= 0) {
+            accept = 1;
+        } else {
+            uint32_t th = row[dE < Dmax ? dE : Dmax];
+            if (th == 0) {
+                accept = 0;
+            } else {
+                (*drw)++;
+                accept = orc_accept_word(seed, inst, r, (uint32_t)s, t, c) < th;
+            }
+        }
+        if (accept) {
+            int32_t delta = x[k] ? -1 : 1;
+            x[k] ^= 1;
+            for (int32_t l = 0; l < N; l++)
+                if (l != k) h[l] += delta * J_at(J, N, m, W, P, k, l);
+            *E += dE;
+            (*acc)++;
+        }
+    }
+}
+
 /* J may be NULL: then every coefficient comes from orc_J(m, W, P, ., .). */
 int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const int32_t *b, int64_t c0,
                    int32_t S, int32_t Dmax, const uint32_t *thr,
@@ -349,31 +382,7 @@ int32_t orc_anneal(int32_t m, const int32_t *J, const int32_t *W, int32_t P, con
         int32_t s0 = start_sweep ? start_sweep[i] : 0;
 
         for (int32_t s = s0; s < S; s++) {
-            const uint32_t *row = thr + (int64_t)s * (Dmax + 1);
-            for (int32_t k = 0; k < N; k++) {
-                int32_t t = k / m + 1, c = k % m;
-                int32_t dE = x[k] ? -h[k] : h[k];
-                int accept;
-                if (dE <= 0) {
-                    accept = 1;
-                } else {
-                    uint32_t th = row[dE < Dmax ? dE : Dmax];
-                    if (th == 0) {
-                        accept = 0;
-                    } else {
-                        drw++;
-                        accept = orc_accept_word(seed, inst, r, (uint32_t)s, t, c) < th;
-                    }
-                }
-                if (accept) {
-                    int32_t delta = x[k] ? -1 : 1;
-                    x[k] ^= 1;
-                    for (int32_t l = 0; l < N; l++)
-                        if (l != k) h[l] += delta * J_at(J, N, m, W, P, k, l);
-                    E += dE;
-                    acc++;
-                }
-            }
+            sweep_once(m, J, W, P, thr + (int64_t)s * (Dmax + 1), Dmax, seed, inst, r, s, x, h, &E, &acc, &drw);
             if (E < bE) {
                 bE = E;
                 bs = s;
@@ -635,5 +644,96 @@ int32_t orc_pt_exchange(int32_t K, int32_t R, int32_t N, uint32_t round, uint32_
         }
     }
     free(tmp);
+    return 0;
+}
+
+/* Parallel tempering of the chains chain_ids[0..n_chain-1], each independent
+ * of the others: slot k of chain r starts from the stream-1 bits of instance
+ * inst + k and sweeps with table row thr[k] (a constant temperature; entries
+ * up to Dmax, zero past the slot's own cutoff) and instance id inst + k; after
+ * sweep s, when (s + 1) is a multiple of `interval` and s + 1 < S, exchange
+ * round e = (s + 1) / interval - 1 runs on the chain's pairs (k = e mod 2,
+ * k + 2, ...) with the rule of orc_pt_exchange, swapping states, fields and
+ * energies.  Each slot keeps its best at its sweep ends.  Outputs per chain i
+ * and slot k at [i][k]; swaps per chain and pair at [i][k]. */
+int32_t orc_pt_anneal(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const int32_t *b, int64_t c0,
+                      int32_t K, int32_t S, int32_t interval, int32_t Dmax, const uint32_t *thr,
+                      const int32_t *DX, int32_t stride, const uint32_t *xthr,
+                      uint32_t seed, uint32_t inst, int32_t n_chain, const int32_t *chain_ids,
+                      uint8_t *final_x, int64_t *final_E, int64_t *best_E, int32_t *best_sweep, uint8_t *best_x,
+                      uint64_t *accepts, uint64_t *draws, uint64_t *swaps, int32_t n_threads)
+{
+    int32_t N = m * m;
+    if (K < 1 || interval < 1) return -1;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int32_t i = 0; i < n_chain; i++) {
+        uint32_t r = (uint32_t)chain_ids[i];
+        uint8_t *xs = final_x + (int64_t)i * K * N;
+        uint8_t *bxs = best_x + (int64_t)i * K * N;
+        int32_t *hs = (int32_t *)malloc(sizeof(int32_t) * (size_t)K * (size_t)(N > 0 ? N : 1));
+        int32_t *htmp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(N > 0 ? N : 1));
+        uint8_t *xtmp = (uint8_t *)malloc((size_t)(N > 0 ? N : 1));
+        int64_t *Es = final_E + (int64_t)i * K, *bE = best_E + (int64_t)i * K;
+        int32_t *bs = best_sweep + (int64_t)i * K;
+        uint64_t *acc = accepts + (int64_t)i * K, *drw = draws + (int64_t)i * K;
+        uint64_t *sw = swaps ? swaps + (int64_t)i * (K > 1 ? K - 1 : 1) : NULL;
+        for (int32_t k = 0; k < K; k++) {
+            uint8_t *x = xs + (int64_t)k * N;
+            int32_t *h = hs + (int64_t)k * N;
+            for (int32_t v = 0; v < N; v++) x[v] = (uint8_t)orc_init_bit(seed, inst + (uint32_t)k, r, v / m + 1, v % m);
+            for (int32_t v = 0; v < N; v++) {
+                int32_t f = b[v];
+                for (int32_t l = 0; l < N; l++)
+                    if (l != v && x[l]) f += J_at(J, N, m, W, P, v, l);
+                h[v] = f;
+            }
+            Es[k] = qubo_energy_any(m, J, W, P, b, c0, x);
+            bE[k] = INT64_MAX;
+            bs[k] = -1;
+            acc[k] = drw[k] = 0;
+            memcpy(bxs + (int64_t)k * N, x, (size_t)N);
+        }
+        if (sw)
+            for (int32_t k = 0; k + 1 < K; k++) sw[k] = 0;
+        for (int32_t s = 0; s < S; s++) {
+            for (int32_t k = 0; k < K; k++) {
+                uint8_t *x = xs + (int64_t)k * N;
+                sweep_once(m, J, W, P, thr + (int64_t)k * (Dmax + 1), Dmax, seed, inst + (uint32_t)k, r, s, x,
+                           hs + (int64_t)k * N, &Es[k], &acc[k], &drw[k]);
+                if (Es[k] < bE[k]) {
+                    bE[k] = Es[k];
+                    bs[k] = s;
+                    memcpy(bxs + (int64_t)k * N, x, (size_t)N);
+                }
+            }
+            if (K < 2 || (s + 1) % interval != 0 || s + 1 >= S) continue;
+            uint32_t e = (uint32_t)((s + 1) / interval - 1);
+            for (int32_t k = (int32_t)(e & 1u); k + 1 < K; k += 2) {
+                int64_t d = Es[k + 1] - Es[k];
+                int accept;
+                if (d >= 0) {
+                    accept = 1;
+                } else {
+                    int64_t a = -d;
+                    uint32_t th = xthr[(int64_t)k * stride + (a < DX[k] ? a : DX[k])];
+                    accept = th != 0 && orc_pt_word(seed, inst, r, e, k) < th;
+                }
+                if (!accept) continue;
+                uint8_t *x0 = xs + (int64_t)k * N, *x1 = xs + (int64_t)(k + 1) * N;
+                int32_t *h0 = hs + (int64_t)k * N, *h1 = hs + (int64_t)(k + 1) * N;
+                memcpy(xtmp, x0, (size_t)N); memcpy(x0, x1, (size_t)N); memcpy(x1, xtmp, (size_t)N);
+                memcpy(htmp, h0, sizeof(int32_t) * (size_t)N); memcpy(h0, h1, sizeof(int32_t) * (size_t)N);
+                memcpy(h1, htmp, sizeof(int32_t) * (size_t)N);
+                int64_t t = Es[k]; Es[k] = Es[k + 1]; Es[k + 1] = t;
+                if (sw) sw[k]++;
+            }
+        }
+        free(hs);
+        free(htmp);
+        free(xtmp);
+    }
     return 0;
 }

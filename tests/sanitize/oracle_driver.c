@@ -30,6 +30,12 @@ void orc_pt_tables(double T_hot, double T_cold, int32_t K, const int32_t *DX, in
 int32_t orc_pt_exchange(int32_t K, int32_t R, int32_t N, uint32_t round, uint32_t seed, uint32_t inst,
                         const int32_t *DX, int32_t stride, const uint32_t *xthr, uint8_t *x, int64_t *E,
                         uint64_t *swaps);
+int32_t orc_pt_anneal(int32_t m, const int32_t *J, const int32_t *W, int32_t P, const int32_t *b, int64_t c0,
+                      int32_t K, int32_t S, int32_t interval, int32_t Dmax, const uint32_t *thr,
+                      const int32_t *DX, int32_t stride, const uint32_t *xthr,
+                      uint32_t seed, uint32_t inst, int32_t n_chain, const int32_t *chain_ids,
+                      uint8_t *final_x, int64_t *final_E, int64_t *best_E, int32_t *best_sweep, uint8_t *best_x,
+                      uint64_t *accepts, uint64_t *draws, uint64_t *swaps, int32_t n_threads);
 
 #define CHECK(c)                                                                \
     do {                                                                        \
@@ -117,6 +123,28 @@ int main(void)
         for (int i = 0; i < K * R * N; i++) x[i] = (uint8_t)(i & 1);
         for (int i = 0; i < K * R; i++) E[i] = (int64_t)((i * 37) % 101) - 20;
         for (uint32_t rnd = 0; rnd < 5; rnd++) CHECK(orc_pt_exchange(K, R, N, rnd, 3, 1, DX, mx + 1, xt, x, E, sw) == 0);
+        /* a whole tempering run of two chains on the 3x3 field (J computed on the fly) */
+        {
+            int32_t F[9], W[100], b[64];
+            uint8_t nf[9] = {0};
+            int32_t m = orc_free_cells(3, 3, 0, nf, F);
+            int32_t wmax = orc_cost_matrix(3, 0, m, F, 10, W);
+            int64_t c0 = 0;
+            int32_t *Jf = (int32_t *)malloc(sizeof(int32_t) * 64 * 64);
+            orc_build_qubo(m, W, 2 * wmax, 1, Jf, b, &c0);
+            int32_t Dm = orc_dmax(90.0);
+            uint32_t *tt = (uint32_t *)calloc((size_t)K * (size_t)(Dm + 1), sizeof(uint32_t));
+            for (int k = 0; k < K; k++) orc_thresholds(90.0 - 10.0 * k, 90.0 - 10.0 * k, 1, Dm, tt + (size_t)k * (Dm + 1));
+            int32_t ch[2] = {0, 5};
+            uint8_t fx[2 * K * 64], bx[2 * K * 64];
+            int64_t fE[2 * K], bE2[2 * K];
+            int32_t bs2[2 * K];
+            uint64_t ac[2 * K], dr[2 * K], sw2[2 * (K - 1)];
+            CHECK(orc_pt_anneal(m, NULL, W, 2 * wmax, b, c0, K, 12, 2, Dm, tt, DX, mx + 1, xt, 1, 0, 2, ch, fx, fE, bE2,
+                                bs2, bx, ac, dr, sw2, 1) == 0);
+            free(tt);
+            free(Jf);
+        }
         free(xt);
     }
     printf("oracle driver: clean\n");

@@ -154,3 +154,19 @@ def test_pt_slots_sample_boltzmann(oracle_lib):
         mean, var = (p * Eall).sum(), (p * Eall ** 2).sum() - ((p * Eall).sum()) ** 2
         emp = pt["final_E"][k].astype(np.float64)
         assert abs(emp.mean() - mean) < 5 * np.sqrt(var / R) + 1e-9, (k, emp.mean(), mean)
+
+
+@pytest.mark.parametrize("K,interval,closed", [(4, 1, True), (5, 3, False), (1, 2, True)])
+def test_chain_loop_equals_composition(oracle_lib, K, interval, closed):
+    """The one-loop-per-chain tempering (fields kept across rounds) equals the
+    composition of plain anneals and exchange rounds, for all chains and for
+    a subset of chain ids."""
+    q = oracle_lib.OracleQubo(3, 4, closed=closed)
+    R, S = 9, 25
+    ref = oracle_lib.pt_anneal(q, K, R, S, 60.0, 2.0, 4, 6, interval=interval)
+    for chains in (list(range(R)), [7, 2]):
+        got = oracle_lib.pt_anneal_chains(q, K, chains, S, 60.0, 2.0, 4, 6, interval=interval)
+        for f in ("final_x", "final_E", "best_E", "best_sweep", "best_x", "accepts", "draws"):
+            assert np.array_equal(got[f], np.swapaxes(ref[f], 0, 1)[chains]), (f, chains)
+        if K > 1 and len(chains) == R:
+            assert np.array_equal(got["swaps"].sum(0), ref["swaps"])
