@@ -131,3 +131,35 @@ def test_instance_schedules_equal_separate_plans(U, oracle_lib):
     r0 = plan.rep_offset[1]
     assert np.array_equal(out.final_E[r0:r0 + R].cpu().numpy(), ref["final_E"])
     assert np.array_equal(out.best_E[r0:r0 + R].cpu().numpy(), ref["best_E"])
+
+
+@pytest.mark.parametrize("interval", [1, 10])
+def test_tempering_full_size_sampled_chains(U, oracle_lib, interval):
+    """The tempering study's configuration at full size (8x8 field with no-fly
+    cells, K = 16 slots x R = 64 chains, 1000 sweeps, ladder 100 -> 0.5):
+    sampled chains, every slot, bit-exact with the oracle's per-chain loop."""
+    import torch
+    g = inputs.grid(8, 8, 0.1, seed=1, inst=0)
+    K, R, S = 16, 64, 1000
+    chains = [0, 1, 13, 31, 32, 47, 62, 63]
+    say(f"case: tempering full size K={K} R={R} S={S} interval={interval}")
+    q = U.qubo_build(g.rows, g.cols, nofly=g.nofly)
+    pt = U.ParallelTempering(q, g.inst_id, K, R, S, 100.0, 0.5, seed=1, interval=interval)
+    res = pt.run()
+    torch.cuda.synchronize()
+    o = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly)
+    ref = oracle_lib.pt_anneal_chains(o, K, chains, S, 100.0, 0.5, 1, g.inst_id, interval=interval, threads=8)
+    W = q.state_words
+    h = {f: res[f].cpu().numpy() for f in ("states", "E", "best_E", "best_sweep", "best_states", "accepts", "draws")}
+    for i, r in enumerate(chains):
+        for k in range(K):
+            assert np.array_equal(U.unpack_states(h["states"][k, r].view(np.uint32)[None], q.m)[0],
+                                  ref["final_x"][i, k]), (r, k, "final_x")
+            assert h["E"][k, r] == ref["final_E"][i, k], (r, k)
+            assert h["best_E"][k, r] == ref["best_E"][i, k], (r, k)
+            assert h["best_sweep"][k, r] == ref["best_sweep"][i, k], (r, k)
+            assert np.array_equal(U.unpack_states(h["best_states"][k, r].view(np.uint32)[None], q.m)[0],
+                                  ref["best_x"][i, k]), (r, k, "best_x")
+            assert int(h["accepts"][k, r]) == int(ref["accepts"][i, k]), (r, k)
+            assert int(h["draws"][k, r]) == int(ref["draws"][i, k]), (r, k)
+    assert ref["swaps"].sum() > 0
