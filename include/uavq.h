@@ -152,8 +152,8 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
 
 /* Launch shape chosen by uavq_autotune (never changes results). */
 typedef struct {
-    int32_t waves_per_block[5];  /* per chunk class c = ceil(m/64) (index 0 unused); 0 = default;
-                                    class 4 runs at most 4 per block */
+    int32_t waves_per_block[7];  /* per chunk class c = ceil(m/64) (index 0 unused); 0 = default;
+                                    classes 4..6 run at most 4 per block */
     uint32_t variant_flags;      /* 0, UAVQ_VARIANT_ROWMASK and/or UAVQ_VARIANT_NOPRODUCER */
     float trial_ms;              /* measured time of the chosen shape (trial run) */
 } uavq_tune;
@@ -191,7 +191,7 @@ typedef struct {
 } uavq_plan_info_t;
 int uavq_plan_info(const uavq_plan *plan, uavq_plan_info_t *info);
 /* Name of the sweep kernel that uavq_anneal_batch launches for the
- * instances of chunk class cls (1: m <= 64, 2: m <= 128, 3: m <= 192, 4: m <= 256), for
+ * instances of chunk class cls (1: m <= 64, 2: m <= 128, ..., 6: m <= 384), for
  * profiling and reports: "" if the class is empty, NULL on error (cls out of
  * range, or no HIP device to decide the launch shape on).  The string is
  * static. */

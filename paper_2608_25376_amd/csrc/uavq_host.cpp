@@ -477,7 +477,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     for (int cls = 1; cls <= kMaxChunks; cls++) {
         int wpb = p->waves_per_block ? p->waves_per_block : default_waves_per_block(cls);
         if (p->tune && p->tune->waves_per_block[cls] > 0) wpb = p->tune->waves_per_block[cls];
-        if (cls == kMaxChunks && wpb > kWideMaxWaves) wpb = kWideMaxWaves;   // that kernel's block limit
+        if (cls >= 4 && wpb > kWideMaxWaves) wpb = kWideMaxWaves;   // those kernels' block limit
         if (wpb < 1 || wpb > 16) {
             delete pl;
             return set_error(UAVQ_EINVAL, "plan_create: waves per block %d out of range", wpb);

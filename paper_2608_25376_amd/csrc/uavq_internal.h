@@ -12,9 +12,9 @@ namespace uavq {
 
 // Largest number of 64-column chunks a replica row may span in the factored
 // kernel (m <= 64 * kMaxChunks).
-constexpr int kMaxChunks = 4;
+constexpr int kMaxChunks = 6;
 constexpr int kMaxM = 64 * kMaxChunks;
-constexpr int kWideMaxWaves = 4;   // waves per block of the last class's kernel
+constexpr int kWideMaxWaves = 4;   // waves per block of the kernels of classes 4..kMaxChunks
 
 int set_error(int code, const char *fmt, ...);
 

@@ -31,7 +31,7 @@
 // block-start state, which finishes most blocks at low temperature without
 // the walk.  When one replica runs per SIMD (k_sweep_ylds_pc) a second wave
 // per replica computes the next sweep's random words and acceptance cuts.
-// m <= 256 (k_sweep_factored): lane L holds the cell masks of steps
+// m <= 384 (k_sweep_factored*): lane L holds the cell masks of steps
 // L + 1 + 64 j (bits = cells) and the occupation count of cells L + 64 j, and
 // travel rows are rebuilt from the neighbouring steps' masks.
 // The cost matrix D, the start-cell costs and one row of the acceptance table
@@ -624,6 +624,20 @@ __global__ __launch_bounds__(64 * kWideMaxWaves) __attribute__((amdgpu_waves_per
         const int itx = next_item(a, iter);
         if (itx < 0) break;
         factored_item<4, STOP>(a, itx, smem);
+    }
+}
+
+// Classes 5 and 6 (m <= 384, fields up to 19x19 with 8-bit costs): the same
+// chunked walk; the lane's step masks (up to 72 words) leave room for one wave
+// per SIMD only, and part of the per-lane arrays lives in scratch memory.
+template <int NJ, bool STOP>
+__global__ __launch_bounds__(64 * kWideMaxWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_sweep_factored_wide(
+    KArgs a) {
+    extern __shared__ __align__(16) uint8_t smem[];
+    for (int iter = 0;; iter++) {
+        const int itx = next_item(a, iter);
+        if (itx < 0) break;
+        factored_item<NJ, STOP>(a, itx, smem);
     }
 }
 
@@ -1223,7 +1237,9 @@ static const void *class_kernel_t(const uavq_plan *pl, int cls) {
     if (cls == 1) return (const void *)k_sweep_factored<1, STOP>;
     if (cls == 2) return (const void *)k_sweep_factored<2, STOP>;
     if (cls == 3) return (const void *)k_sweep_factored<3, STOP>;
-    return (const void *)k_sweep_factored4<STOP>;
+    if (cls == 4) return (const void *)k_sweep_factored4<STOP>;
+    if (cls == 5) return (const void *)k_sweep_factored_wide<5, STOP>;
+    return (const void *)k_sweep_factored_wide<6, STOP>;
 }
 
 static const void *class_kernel(const uavq_plan *pl, int cls) {
@@ -1382,8 +1398,10 @@ const char *uavq_plan_kernel_name(const uavq_plan *pl, int32_t cls) {
     if (uavq::prepare(pl)) return nullptr;   // the one-wave choice needs the device's CU count
     if (cls == 1 && uavq::use_ylds(pl) && pl->ylds_pc) return "k_sweep_ylds_pc";
     if (cls == 1 && uavq::use_ylds(pl)) return pl->ylds_w1 ? "k_sweep_ylds_w1" : "k_sweep_ylds";
-    return cls == 1 ? "k_sweep_factored<1>"
-                    : (cls == 2 ? "k_sweep_factored<2>" : (cls == 3 ? "k_sweep_factored<3>" : "k_sweep_factored4"));
+    static const char *const names[] = {"", "k_sweep_factored<1>", "k_sweep_factored<2>", "k_sweep_factored<3>",
+                                        "k_sweep_factored4", "k_sweep_factored_wide<5>", "k_sweep_factored_wide<6>"};
+    static_assert(sizeof(names) / sizeof(names[0]) == uavq::kMaxChunks + 1, "one name per chunk class");
+    return names[cls];
 }
 
 int uavq_anneal_batch(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
@@ -1558,10 +1576,23 @@ static bool cache_lookup(const char *path, const std::string &key, uavq_tune *t)
         char *q2 = strchr(q1 + 1, '"');
         if (!q2) continue;
         if (std::string(q1 + 1, q2) != key) continue;
+        // "wpb": [one value per chunk class], "variant": u, "ms": f (a line of
+        // another class count does not parse and is tuned again)
         uavq_tune v{};
+        const char *w = strstr(q2 + 1, "\"wpb\": [");
+        bool ok = w != nullptr;
+        if (ok) w += 8;
+        for (int c = 1; ok && c <= kMaxChunks; c++) {
+            char *end = nullptr;
+            const long x = strtol(w, &end, 10);
+            ok = end != w && x >= 0 && x <= 16;
+            if (!ok) break;
+            v.waves_per_block[c] = (int32_t)x;
+            w = end;
+            if (c < kMaxChunks) ok = *w++ == ',';
+        }
         unsigned var = 0;
-        if (sscanf(q2 + 1, ": {\"wpb\": [%d, %d, %d, %d], \"variant\": %u, \"ms\": %f}", &v.waves_per_block[1],
-                   &v.waves_per_block[2], &v.waves_per_block[3], &v.waves_per_block[4], &var, &v.trial_ms) == 6) {
+        if (ok && sscanf(w, "], \"variant\": %u, \"ms\": %f}", &var, &v.trial_ms) == 2) {
             v.variant_flags = var;
             *t = v;
             found = true;
@@ -1586,11 +1617,11 @@ static void cache_store(const char *path, const std::string &key, const uavq_tun
         }
         fclose(f);
     }
-    char buf[512];
-    snprintf(buf, sizeof buf, "\"%s\": {\"wpb\": [%d, %d, %d, %d], \"variant\": %u, \"ms\": %.4f}", key.c_str(),
-             t.waves_per_block[1], t.waves_per_block[2], t.waves_per_block[3], t.waves_per_block[4],
-             (unsigned)t.variant_flags, t.trial_ms);
-    keep.push_back(buf);
+    std::string entry = "\"" + key + "\": {\"wpb\": [";
+    for (int c = 1; c <= kMaxChunks; c++) entry += std::to_string(t.waves_per_block[c]) + (c < kMaxChunks ? ", " : "");
+    char buf[96];
+    snprintf(buf, sizeof buf, "], \"variant\": %u, \"ms\": %.4f}", (unsigned)t.variant_flags, t.trial_ms);
+    keep.push_back(entry + buf);
     std::string tmp = std::string(path) + ".tmp";
     FILE *f = fopen(tmp.c_str(), "w");
     if (!f) return;

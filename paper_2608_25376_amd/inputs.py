@@ -82,6 +82,9 @@ def workload(name: str) -> Workload:
     if name == "grid16x16":
         return Workload(name, [grid(16, 16)], 4096, 1000, 200.0, 0.5, 1,
                         "16x16, no obstacles, 255 free cells, 65025 vars (the largest factored class)")
+    if name == "grid19x19":
+        return Workload(name, [grid(19, 19)], 4096, 1000, 200.0, 0.5, 1,
+                        "19x19, no obstacles, 360 free cells, 129600 vars (the largest field with 8-bit costs)")
     if name == "batch256":
         return Workload(name, batch(256, 1), 256, 2000, 200.0, 0.5, 1,
                         "256 instances, side U{4..10}, density U[0,0.2]")

@@ -24,7 +24,7 @@ PERSISTENT = 0x20
 GRAPH = 0x40
 VARIANT_NOPRODUCER = 0x80
 STOP_FROZEN = 0x100
-CHUNK_CLASSES = 4          # sweep kernel classes by ceil(m / 64); m <= 256
+CHUNK_CLASSES = 6          # sweep kernel classes by ceil(m / 64); m <= 384
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
 
@@ -49,7 +49,7 @@ class _QuboInfo(C.Structure):
 
 class Tune(C.Structure):
     """Launch shape chosen by autotune (per chunk class c = ceil(m/64))."""
-    _fields_ = [("waves_per_block", C.c_int32 * 5), ("variant_flags", C.c_uint32), ("trial_ms", C.c_float)]
+    _fields_ = [("waves_per_block", C.c_int32 * 7), ("variant_flags", C.c_uint32), ("trial_ms", C.c_float)]
 
     def __repr__(self):
         return (f"Tune(waves_per_block={list(self.waves_per_block)[1:]}, variant={self.variant_flags:#x}, "

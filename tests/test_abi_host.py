@@ -119,7 +119,7 @@ def test_validation_errors(U):
         U.Plan([q], [0], 4, 10, 1.0, 10.0)       # T1 <= T0
     with pytest.raises(U.UavqError):
         U.Plan([q], [0], 4, 10, 10.0, 1.0, dense=True)   # dense kernel needs the dense J
-    big = U.qubo_build(17, 17)                   # m = 288 > 256
+    big = U.qubo_build(20, 20, cost_scale=5)     # m = 399 > 384 (w_max 134 at this cost scale)
     with pytest.raises(U.UavqError) as e:
         U.Plan([big], [0], 4, 10, 10.0, 1.0)
     assert e.value.code == U.ETOOBIG
@@ -153,10 +153,11 @@ def test_plan_kernel_name_without_device(U):
     q = U.qubo_build(3, 3, dense=True)
     p = U.Plan([q], [0], 4, 10, 10.0, 1.0)
     with pytest.raises(U.UavqError):
-        p.kernel_name(0)                          # classes are 1..4
+        p.kernel_name(0)                          # classes are 1..6
     with pytest.raises(U.UavqError):
-        p.kernel_name(5)
+        p.kernel_name(7)
     assert p.kernel_name(4) == ""                 # no instance with 192 < m <= 256
+    assert p.kernel_name(6) == ""                 # no instance with 320 < m <= 384
     assert p.kernel_name(2) == ""                 # no instance with 64 < m <= 128
     pd = U.Plan([q], [0], 4, 10, 10.0, 1.0, dense=True)
     assert pd.kernel_name(1) == "k_sweep_dense"

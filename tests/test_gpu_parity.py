@@ -132,6 +132,37 @@ def test_fourth_class_fields(U, oracle_lib, side, dens, inst):
     compare_replicas(gi, orc, reps, f"{side}x{side}")
 
 
+@pytest.mark.parametrize("side,dens,inst,cls", [(18, 0.1, 14, 5), (19, 0.05, 15, 6)])
+def test_fifth_and_sixth_class_fields(U, oracle_lib, side, dens, inst, cls):
+    """256 < m <= 384 (up to 19x19 fields, 121,801 variables at m = 349): the
+    one-wave-per-SIMD chunked kernels against the oracle (coefficients from
+    their definition) on two replicas started from random tours over a short
+    hot schedule; every replica's energy agrees with the host evaluation of
+    its final state (the MFMA check's LDS does not reach these sizes)."""
+    g = inputs.grid(side, side, dens, seed=2, inst=inst)
+    m = g.n_free
+    assert (m + 63) // 64 == cls
+    R, S, T0, T1 = 6, 3, 150.0, 50.0
+    rng = np.random.default_rng(inst)
+    x0 = np.zeros((R, m * m), np.uint8)
+    for r in range(R):
+        X = np.zeros((m, m), np.uint8)
+        X[np.arange(m), rng.permutation(m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = np.array([1, 0, 0, 1, 0, 1], np.uint8)
+    say(f"case: class {cls} {side}x{side} m={m} R={R} S={S}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, 3, init_x=[x0], seeded=seeded)
+    assert plan.kernel_name(cls) == f"k_sweep_factored_wide<{cls}>"
+    gi = split(U, qs, plan, res)[0]
+    q = qs[0]
+    E_host = U.energy_eval(q, res["final_states"].view(np.uint32).reshape(R, q.state_words))
+    assert np.array_equal(E_host, gi["final_E"])
+    o = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, dense=False)
+    reps = [0, R - 1]
+    orc = oracle_lib.anneal(o, S, T0, T1, 3, g.inst_id, reps, init_x=x0[reps], threads=2)
+    compare_replicas(gi, orc, reps, f"{side}x{side}")
+
+
 @pytest.mark.parametrize("rows,cols,dens,inst,closed", [
     (1, 2, 0.0, 0, True), (3, 3, 0.0, 1, True), (5, 5, 0.0, 3, False), (8, 8, 0.1, 0, True)])
 def test_rowmask_variant(U, oracle_lib, rows, cols, dens, inst, closed):
