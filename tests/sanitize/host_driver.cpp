@@ -90,7 +90,7 @@ static int one_field(const Field &f, std::vector<uavq_qubo *> &keep) {
 int main() {
     const Field fields[] = {{1, 2, 0, 0},  {3, 3, 0, UAVQ_DENSE}, {3, 4, 0, UAVQ_OPEN_PATH | UAVQ_DENSE},
                             {5, 5, 20, UAVQ_DENSE}, {2, 9, 30, UAVQ_OPEN_PATH}, {8, 8, 10, 0},
-                            {12, 12, 0, 0}, {16, 16, 5, UAVQ_OPEN_PATH}, {4, 4, 100, 0}};
+                            {12, 12, 0, 0}, {16, 16, 5, UAVQ_OPEN_PATH}, {19, 19, 3, 0}, {4, 4, 100, 0}};
     std::vector<uavq_qubo *> qs;
     for (const Field &f : fields)
         if (one_field(f, qs)) return 1;
