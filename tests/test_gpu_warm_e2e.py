@@ -1,8 +1,8 @@
 """End-to-end warm start on the GPU at a small scale: label instances with
 the annealer, train the network with the library's kernels, sample seed
 tours, anneal with half of the replicas seeded, and run the time-to-target
-protocol.  The gain itself is reported, not asserted; the test
-checks that every piece is wired as specified."""
+protocol.  The gain itself is measured by the protocol's full run, not
+asserted here; the test checks that every piece is wired as specified."""
 import numpy as np
 import pytest
 
