@@ -119,6 +119,8 @@ def test_validation_errors(U):
         U.Plan([q], [0], 4, 10, 1.0, 10.0)       # T1 <= T0
     with pytest.raises(U.UavqError):
         U.Plan([q], [0], 4, 10, 10.0, 1.0, dense=True)   # dense kernel needs the dense J
+    ok = U.Plan([U.qubo_build(19, 19)], [0], 4, 10, 10.0, 1.0)   # m = 360: the sixth chunk class
+    assert ok.total_state_words == 4 * 360 * 12
     big = U.qubo_build(20, 20, cost_scale=5)     # m = 399 > 384 (w_max 134 at this cost scale)
     with pytest.raises(U.UavqError) as e:
         U.Plan([big], [0], 4, 10, 10.0, 1.0)
