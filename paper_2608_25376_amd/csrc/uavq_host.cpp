@@ -425,7 +425,19 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         sched_of[i] = (int32_t)j;
     }
     pl->thr_rows = sched_row.empty() ? 1 : sched_row.back() + sched_rows.back();
-    std::vector<uint32_t> thr_dev((size_t)pl->thr_rows * pl->thr_stride, 0u);
+    if ((double)pl->thr_rows * pl->thr_stride * 4.0 > 4.0 * (1ull << 30)) {
+        const int32_t rows = pl->thr_rows, stride = pl->thr_stride;
+        delete pl;
+        return set_error(UAVQ_ETOOBIG, "plan_create: acceptance tables of %d rows x %d entries exceed 4 GiB", rows,
+                         stride);
+    }
+    std::vector<uint32_t> thr_dev;
+    try {
+        thr_dev.assign((size_t)pl->thr_rows * pl->thr_stride, 0u);
+    } catch (...) {
+        delete pl;
+        return set_error(UAVQ_ENOMEM, "plan_create: out of host memory for the acceptance tables");
+    }
     for (size_t j = 0; j < sched_row.size(); j++)
         fill_schedule(uT[2 * j], uT[2 * j + 1], sched_rows[j], Dmax,
                       thr_dev.data() + (size_t)sched_row[j] * pl->thr_stride, pl->thr_stride);

@@ -234,3 +234,14 @@ def test_plan_instance_schedules_host(U):
             U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1, inst_T=bad)
     # a constant schedule never grows its cutoff, so it is allowed with UAVQ_STOP_FROZEN
     U.Plan([q, q], [0, 1], R, S, 50.0, 0.5, 1, inst_T=[(50.0, 0.5), (5.0, 5.0)], stop_frozen=True)
+
+
+def test_plan_table_size_limit(U):
+    """Many distinct cooling schedules in one plan: refused before any
+    allocation once the tables would pass 4 GiB."""
+    q = U.qubo_build(4, 4)
+    n = 70
+    sch = [(200.0, 0.5 + 0.01 * i) for i in range(n)]   # 70 x 4000 rows x 4440 entries x 4 B ~ 5 GB
+    with pytest.raises(U.UavqError) as e:
+        U.Plan([q] * n, list(range(n)), 2, 4000, 200.0, 0.5, 1, inst_T=sch)
+    assert e.value.code == U.ETOOBIG
