@@ -76,7 +76,8 @@ def aux_measurements(args):
     per state, two byte limbs, int32 accumulation) at the 12x12 and 8x8 sizes,
     and one forward+backward step of the warm-start network (bf16 operands,
     fp32 accumulation) on a batch of 32 fields of 10x10, eager and replayed
-    from a captured HIP graph."""
+    from a captured HIP graph; the time to result with UAVQ_STOP_FROZEN; and
+    parallel tempering against the plain anneal of the same replica-sweeps."""
     import numpy as np
     import torch
     from paper_2608_25376_amd import inputs, uavq
@@ -115,6 +116,26 @@ def aux_measurements(args):
         row["identical_outputs"] = all(np.array_equal(x, y) for x, y in zip(outs[False], outs[True]))
         row["value"] = row["stop"]
         print(json.dumps(row), flush=True)
+    # parallel tempering on the bench field: 16 slots x 64 chains, 1000 sweeps, one launch per
+    # exchange round; attempts/s counts every slot's sweeps (the same count as the plain anneal of
+    # 1024 replicas x 1000 sweeps, timed beside it)
+    w = inputs.workload("grid8x8_nofly0.1")
+    g = w.grids[0]
+    q = uavq.qubo_build(g.rows, g.cols, nofly=g.nofly)
+    K, R, S = 16, 64, 1000
+    attempts = float(K * R * S * q.n_vars)
+    plain = uavq.Plan([q], [g.inst_id], K * R, S, 100.0, 0.5, 1)
+    plain.upload()
+    pout = plain.alloc_outputs()
+    row = {"metric": "spin-flip attempts/s, parallel tempering", "unit": "attempts/s",
+           "config": {"workload": w.name, "slots": K, "chains": R, "sweeps": S, "T_hot": 100.0, "T_cold": 0.5},
+           "plain_ms": _time_ms(lambda: plain.anneal(out=pout), 3)}
+    for iv in (1, 10):
+        pt = uavq.ParallelTempering(q, g.inst_id, K, R, S, 100.0, 0.5, seed=1, interval=iv)
+        row[f"interval{iv}_ms"] = _time_ms(pt.run, 2)
+    row["value"] = attempts / (row["interval10_ms"] * 1e-3)
+    row["plain_value"] = attempts / (row["plain_ms"] * 1e-3)
+    print(json.dumps(row), flush=True)
     # warm-start network: 32 fields of 10x10 (about 85 free cells each)
     from paper_2608_25376_amd import warmstart
     grids = inputs.batch(32, seed=1, side=10, density_hi=0.2, first_id=10000)
