@@ -41,12 +41,16 @@ def build(force: bool = True, verbose: bool = False) -> str:
     common = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function"]
     # Packed FP32 instructions stay off in all device code.
     dev = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+    # The chunked walk's per-chunk loops must unroll fully for five and six
+    # chunks (m <= 384), or the lane's arrays move to scratch memory; the other
+    # kernels of the file compile to the same code with or without this.
+    per_file = {"uavq_kernels.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
     objs = []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
         if s.endswith(".hip"):
-            cmd = [hipcc, "-x", "hip"] + dev + common + ["-c", src, "-o", obj]
+            cmd = [hipcc, "-x", "hip"] + dev + common + per_file.get(s, []) + ["-c", src, "-o", obj]
         else:
             cmd = [hipcc, "-x", "c++"] + common + ["-c", src, "-o", obj]
         if verbose:
