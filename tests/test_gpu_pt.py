@@ -163,3 +163,21 @@ def test_tempering_full_size_sampled_chains(U, oracle_lib, interval):
             assert int(h["accepts"][k, r]) == int(ref["accepts"][i, k]), (r, k)
             assert int(h["draws"][k, r]) == int(ref["draws"][i, k]), (r, k)
     assert ref["swaps"].sum() > 0
+
+
+@pytest.mark.parametrize("kw", [{"stop_frozen": True}, {"persistent": True}, {"no_producer": True}])
+def test_tempering_plan_options_equal_default(U, kw):
+    """Plan options that never change results (stopping frozen replicas, whose
+    constant schedules never raise the cutoff; the persistent work queue; the
+    one-wave kernel) give the default tempering run's outputs bit for bit."""
+    import torch
+    g = inputs.grid(7, 8, 0.1, seed=6, inst=3)
+    K, R, S = 6, 48, 60
+    say(f"case: tempering options {kw} K={K} R={R} S={S}")
+    q = U.qubo_build(g.rows, g.cols, nofly=g.nofly)
+    ref = U.ParallelTempering(q, g.inst_id, K, R, S, 90.0, 1.0, seed=4, interval=3).run()
+    got = U.ParallelTempering(q, g.inst_id, K, R, S, 90.0, 1.0, seed=4, interval=3, **kw).run()
+    torch.cuda.synchronize()
+    for f in ("states", "E", "best_E", "best_sweep", "best_states", "accepts", "draws", "inst_best_E", "swaps"):
+        assert torch.equal(got[f], ref[f]), (kw, f)
+    assert got["rounds"] == ref["rounds"]
