@@ -1326,8 +1326,10 @@ int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *c
     if (n_items == 0) return UAVQ_OK;
     a.item_base = 0;
     a.queue = nullptr;
-    hipLaunchKernelGGL(k_init_states, dim3(n_items), dim3(256), 0, st, a);
-    UAVQ_HIP(hipGetLastError());
+    if (!a.resume) {   // a resumed segment continues the working states
+        hipLaunchKernelGGL(k_init_states, dim3(n_items), dim3(256), 0, st, a);
+        UAVQ_HIP(hipGetLastError());
+    }
     int rc;
     if (pl->dense) {
         if ((rc = launch_dense(pl, a, st))) return rc;
