@@ -149,6 +149,9 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
                                       along the schedule: plan_create checks, EINVAL otherwise), so
                                       every output is the same; the launch ends when all are frozen.
                                       Not for throughput measurements: frozen sweeps are not evaluated. */
+#define UAVQ_REDUCE_AT_END 0x200u  /* uavq_anneal_segment fills the per-instance outputs (inst_best_*)
+                                      only in a segment that ends the schedule (s_end = S); earlier
+                                      segments leave them untouched.  Per-replica outputs are unchanged. */
 
 /* Launch shape chosen by uavq_autotune (never changes results). */
 typedef struct {

@@ -401,6 +401,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     pl->no_producer = (p->flags & UAVQ_VARIANT_NOPRODUCER) ? 1 : 0;
     if (p->tune) pl->no_producer = (p->tune->variant_flags & UAVQ_VARIANT_NOPRODUCER) ? 1 : 0;
     pl->stop_frozen = (p->flags & UAVQ_STOP_FROZEN) ? 1 : 0;
+    pl->reduce_at_end = (p->flags & UAVQ_REDUCE_AT_END) ? 1 : 0;
     pl->persistent = (p->flags & UAVQ_PERSISTENT) ? 1 : 0;
     pl->graph = (p->flags & UAVQ_GRAPH) ? 1 : 0;
     const int32_t S = p->sweeps, R = p->replicas;

@@ -121,6 +121,7 @@ struct uavq_plan {
     int32_t ylds_pc = 0;         // ... with a cut-producing wave beside each replica's wave
     int32_t no_producer = 0;     // UAVQ_VARIANT_NOPRODUCER
     int32_t stop_frozen = 0;     // UAVQ_STOP_FROZEN
+    int32_t reduce_at_end = 0;   // UAVQ_REDUCE_AT_END
     size_t queue_off = 0;                 // workspace: item counters (persistent mode)
     void *graph_exec = nullptr;           // cached hipGraphExec_t (graph mode)
     uint64_t graph_key = 0;

@@ -1342,8 +1342,10 @@ int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *c
         for (int cls = 1; cls <= kMaxChunks; cls++)
             if ((rc = launch_class(pl, a, cls, st))) return rc;
     }
-    hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
-    UAVQ_HIP(hipGetLastError());
+    if (!pl->reduce_at_end || a.s_end == pl->S) {
+        hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
+        UAVQ_HIP(hipGetLastError());
+    }
     return check_E ? launch_checks(pl, a, check_E, st) : UAVQ_OK;
 }
 

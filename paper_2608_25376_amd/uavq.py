@@ -24,6 +24,7 @@ PERSISTENT = 0x20
 GRAPH = 0x40
 VARIANT_NOPRODUCER = 0x80
 STOP_FROZEN = 0x100
+REDUCE_AT_END = 0x200
 CHUNK_CLASSES = 6          # sweep kernel classes by ceil(m / 64); m <= 384
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
@@ -315,7 +316,7 @@ class Plan:
     def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
                  T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
                  rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None,
-                 no_producer: bool = False, stop_frozen: bool = False, inst_T=None):
+                 no_producer: bool = False, stop_frozen: bool = False, inst_T=None, reduce_at_end: bool = False):
         """``inst_T``: optional per-instance schedules, a sequence of (T0_i, T1_i)."""
         self.qubos = list(qubos)
         n = len(self.qubos)
@@ -326,6 +327,7 @@ class Plan:
         flags |= (PERSISTENT if persistent else 0) | (GRAPH if graph else 0)
         flags |= VARIANT_NOPRODUCER if no_producer else 0
         flags |= STOP_FROZEN if stop_frozen else 0
+        flags |= REDUCE_AT_END if reduce_at_end else 0
         self._tune = tune
         iT = None
         if inst_T is not None:
@@ -601,7 +603,7 @@ class ParallelTempering:
         self.seed, self.interval = int(seed), int(interval)
         self.T, DX, xthr = pt_ladder(T_hot, T_cold, K)
         self.plan = Plan([q] * K, [(inst_id + k) & 0xFFFFFFFF for k in range(K)], replicas, sweeps, T_hot, T_hot,
-                         seed, inst_T=[(float(t), float(t)) for t in self.T], **plan_kw)
+                         seed, inst_T=[(float(t), float(t)) for t in self.T], reduce_at_end=True, **plan_kw)
         self.plan.upload()
         self.d_DX = torch.from_numpy(np.ascontiguousarray(DX if K > 1 else np.zeros(1, np.int32))).cuda()
         xt = xthr if K > 1 else np.zeros((1, 2), np.uint32)

@@ -208,3 +208,28 @@ def test_energy_check_flags_a_corrupted_state(U):
     U.energy_eval_dev(q, states, E2)
     torch.cuda.synchronize()
     assert list(np.nonzero(E2.cpu().numpy() != final_E)[0]) == [5]
+
+
+def test_reduce_at_end(U):
+    """UAVQ_REDUCE_AT_END: segments before the last leave the per-instance
+    outputs untouched; the last one fills them, and every output equals the
+    straight run's."""
+    import torch
+    gs = [inputs.grid(6, 7, 0.1, seed=3, inst=21), inputs.grid(9, 9, 0.1, seed=3, inst=22)]
+    S, R = 80, 40
+    say(f"case: reduce at end R={R} S={S}")
+    qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in gs]
+    ref_plan = U.Plan(qs, [g.inst_id for g in gs], R, S, 120.0, 0.5, 5)
+    ref_plan.upload()
+    straight = _np(_run(ref_plan, [0, S]))
+    plan = U.Plan(qs, [g.inst_id for g in gs], R, S, 120.0, 0.5, 5, reduce_at_end=True)
+    plan.upload()
+    out = plan.alloc_outputs()
+    out.inst_best_E.fill_(-7)
+    plan.anneal(out=out, s_begin=0, s_end=37)
+    plan.anneal(out=out, s_begin=37, s_end=64, resume=True)
+    torch.cuda.synchronize()
+    assert (out.inst_best_E.cpu().numpy() == -7).all()
+    plan.anneal(out=out, s_begin=64, s_end=S, resume=True)
+    torch.cuda.synchronize()
+    _assert_same(_np(out), straight, "reduce at end")
