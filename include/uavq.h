@@ -345,6 +345,18 @@ int uavq_pt_ladder(double T_hot, double T_cold, int32_t K, double *T, int32_t *D
 int uavq_pt_exchange(int32_t K, int32_t R, int32_t state_words, uint32_t round, uint32_t seed, uint32_t inst_id,
                      const int32_t *d_DX, const uint32_t *d_xthr, int32_t stride, int32_t *d_states, int64_t *d_E,
                      uint64_t *d_swaps, void *stream);
+/* The same round for n_sets chain sets of one plan at once (a batch of
+ * fields, each with K slots of R chains on the same ladder): set i's slots
+ * are instances i*K .. i*K + K - 1 of the plan, its states start at word
+ * d_state_off[i] of d_states ([K][R][d_words[i]]), its energies at
+ * d_E + i*K*R ([K][R]), its draws are addressed by d_inst[i], and its swaps
+ * (if d_swaps) go to d_swaps[i*(K-1) + k].  All arrays are device arrays of
+ * n_sets entries.  Errors as uavq_pt_exchange; n_sets outside 1..65535 is
+ * UAVQ_EINVAL. */
+int uavq_pt_exchange_batch(int32_t n_sets, int32_t K, int32_t R, uint32_t round, uint32_t seed,
+                           const int64_t *d_state_off, const int32_t *d_words, const uint32_t *d_inst,
+                           const int32_t *d_DX, const uint32_t *d_xthr, int32_t stride, int32_t *d_states,
+                           int64_t *d_E, uint64_t *d_swaps, void *stream);
 
 /* Kernel timing for measurement: when enabled, uavq_anneal_batch records HIP
  * events on its stream around the sweep-kernel launches of this plan, and

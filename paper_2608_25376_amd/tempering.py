@@ -73,6 +73,25 @@ def tempering(q, inst, K, R, sweeps, T_hot, T_cold, seed, interval):
             "slot_best_E": bests, "T": [float(t) for t in pt.T]}
 
 
+def batch_study(n, K, R, sweeps, T_hot, T_cold, seed, interval):
+    """n fields of sides 4..10 (no-fly density up to 0.2) tempered as one plan
+    with one batched exchange launch per round, against one tempering run per
+    field; the outputs are identical, only the time differs."""
+    import torch
+    grids = inputs.batch(n, seed=seed)
+    qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in grids]
+    ids = [g.inst_id * K for g in grids]          # disjoint id ranges of K slots
+    bt = uavq.ParallelTemperingBatch(qs, ids, K, R, sweeps, T_hot, T_cold, seed=seed, interval=interval)
+    res, batch_ms = _timed(bt.run)
+    singles = [uavq.ParallelTempering(q, i, K, R, sweeps, T_hot, T_cold, seed=seed, interval=interval)
+               for q, i in zip(qs, ids)]
+    outs, single_ms = _timed(lambda: [p.run() for p in singles])
+    same = all(torch.equal(a["best_E"], b["best_E"]) and torch.equal(a["states"], b["states"])
+               for a, b in zip(res, outs))
+    return {"fields": n, "m": [q.m for q in qs], "K": K, "R": R, "sweeps": sweeps, "interval": interval,
+            "batch_ms": batch_ms, "per_field_ms": single_ms, "identical": bool(same)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--K", type=int, default=16)
@@ -86,10 +105,23 @@ def main():
                     help="also run the plain annealer with this many times the sweeps (about the GPU time of "
                          "tempering with an exchange every 10 sweeps); 0 = skip")
     ap.add_argument("--fields", default="")
+    ap.add_argument("--batch", type=int, default=0, help="only the batch study: this many fields in one plan")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available()
+    if args.batch:
+        q0 = uavq.qubo_build(3, 3)
+        tempering(q0, 0, 2, 8, 4, 10.0, 1.0, 1, 1)     # load the kernels before timing
+        rows = [batch_study(args.batch, args.K, args.R, args.sweeps, args.T_hot, args.T_cold, 1, iv)
+                for iv in [int(v) for v in args.intervals.split(",")]]
+        for r in rows:
+            print(json.dumps(r), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                for r in rows:
+                    f.write(json.dumps(r) + "\n")
+        return
     names = set(args.fields.split(",")) if args.fields else None
     seeds = [int(v) for v in args.seeds.split(",")]
     rows = []

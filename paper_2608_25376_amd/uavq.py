@@ -87,7 +87,7 @@ EXPORTS = [
     "uavq_anneal_batch", "uavq_anneal_segment", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
     "uavq_mlp_param_count", "uavq_mlp_features", "uavq_mlp_workspace_bytes", "uavq_mlp_forward",
     "uavq_mlp_loss_grad", "uavq_mlp_adam", "uavq_quantize_marginals", "uavq_sample_seeds",
-    "uavq_pt_ladder", "uavq_pt_exchange",
+    "uavq_pt_ladder", "uavq_pt_exchange", "uavq_pt_exchange_batch",
 ]
 
 _lib = None
@@ -141,6 +141,8 @@ def lib():
                                      P(C.c_uint32), C.c_int32]
         L.uavq_pt_exchange.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_uint32, C.c_uint32, vp, vp,
                                        C.c_int32, vp, vp, vp, vp]
+        L.uavq_pt_exchange_batch.argtypes = [C.c_int32, C.c_int32, C.c_int32, C.c_uint32, C.c_uint32, vp, vp, vp, vp,
+                                             vp, C.c_int32, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -630,3 +632,70 @@ class ParallelTempering:
                 "best_sweep": out.best_sweep.view(K, R), "best_states": out.best_states.view(K, R, W),
                 "accepts": out.accepts.view(K, R), "draws": out.draws.view(K, R), "inst_best_E": out.inst_best_E,
                 "inst_best_state": out.inst_best_state.view(K, W), "swaps": swaps[:K - 1], "rounds": rnd}
+
+
+class ParallelTemperingBatch:
+    """Parallel tempering of a batch of fields in one plan: field i has K slots
+    of R chains on the same ladder (instances i*K .. i*K + K - 1 of the plan,
+    instance ids inst_ids[i] + k, the constant schedule T_k), and one
+    uavq_pt_exchange_batch launch exchanges every field's pairs.  Field i's
+    outputs equal those of ParallelTempering(q_i, inst_ids[i], ...).  The id
+    ranges inst_ids[i] .. inst_ids[i] + K - 1 must not overlap."""
+
+    def __init__(self, qs: Sequence[Qubo], inst_ids: Sequence[int], K: int, replicas: int, sweeps: int,
+                 T_hot: float, T_cold: float, seed: int = 1, interval: int = 1, **plan_kw):
+        import torch
+        if interval < 1:
+            raise ValueError("interval must be >= 1")
+        ids = [int(v) for v in inst_ids]
+        if len(ids) != len(qs):
+            raise ValueError("one instance id per field")
+        spans = sorted((v, v + K - 1) for v in ids)
+        if any(b[0] <= a[1] for a, b in zip(spans, spans[1:])):
+            raise ValueError("the id ranges inst_ids[i] .. inst_ids[i] + K - 1 overlap")
+        self.qs, self.ids, self.K, self.R, self.S = list(qs), ids, int(K), int(replicas), int(sweeps)
+        self.seed, self.interval = int(seed), int(interval)
+        self.T, DX, xthr = pt_ladder(T_hot, T_cold, K)
+        n = len(self.qs)
+        self.plan = Plan([q for q in self.qs for _ in range(K)], [(v + k) & 0xFFFFFFFF for v in ids for k in range(K)],
+                         replicas, sweeps, T_hot, T_hot, seed,
+                         inst_T=[(float(t), float(t)) for _ in range(n) for t in self.T], reduce_at_end=True, **plan_kw)
+        self.plan.upload()
+        self.d_DX = torch.from_numpy(np.ascontiguousarray(DX if K > 1 else np.zeros(1, np.int32))).cuda()
+        xt = xthr if K > 1 else np.zeros((1, 2), np.uint32)
+        self.d_xthr = torch.from_numpy(np.ascontiguousarray(xt).view(np.int32)).cuda()
+        self.state_off = [int(self.plan.state_offset[i * K]) for i in range(n)]
+        self.d_state_off = torch.tensor(self.state_off, dtype=torch.int64, device="cuda")
+        self.d_words = torch.tensor([q.state_words for q in self.qs], dtype=torch.int32, device="cuda")
+        self.d_inst = torch.from_numpy(np.array(ids, dtype=np.uint32).view(np.int32)).cuda()
+
+    def run(self, stream=None) -> list:
+        """The whole schedule; returns one dict per field, shaped like
+        ParallelTempering.run's (views of the plan's outputs)."""
+        import torch
+        K, R, n = self.K, self.R, len(self.qs)
+        out = self.plan.alloc_outputs()
+        swaps = torch.zeros(n * max(K - 1, 1), dtype=torch.int64, device="cuda")
+        b, rnd = 0, 0
+        while b < self.S:
+            end = min(b + self.interval, self.S)
+            self.plan.anneal(out=out, s_begin=b, s_end=end, resume=b > 0, stream=stream)
+            if end < self.S and K > 1:
+                _check(lib().uavq_pt_exchange_batch(n, K, R, rnd & 0xFFFFFFFF, self.seed & 0xFFFFFFFF,
+                                                    _dptr(self.d_state_off), _dptr(self.d_words), _dptr(self.d_inst),
+                                                    _dptr(self.d_DX), _dptr(self.d_xthr), int(self.d_xthr.shape[1]),
+                                                    _dptr(out.final_states), _dptr(out.final_E), _dptr(swaps),
+                                                    _stream_handle(stream)))
+                rnd += 1
+            b = end
+        res = []
+        for i, q in enumerate(self.qs):
+            W, o = q.state_words, self.state_off[i]
+            rs = slice(i * K * R, (i + 1) * K * R)
+            res.append({"states": out.final_states[o:o + K * R * W].view(K, R, W), "E": out.final_E[rs].view(K, R),
+                        "best_E": out.best_E[rs].view(K, R), "best_sweep": out.best_sweep[rs].view(K, R),
+                        "best_states": out.best_states[o:o + K * R * W].view(K, R, W),
+                        "accepts": out.accepts[rs].view(K, R), "draws": out.draws[rs].view(K, R),
+                        "inst_best_E": out.inst_best_E[i * K:(i + 1) * K],
+                        "swaps": swaps.view(n, max(K - 1, 1))[i, :K - 1], "rounds": rnd})
+        return res

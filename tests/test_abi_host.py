@@ -245,3 +245,14 @@ def test_plan_table_size_limit(U):
     with pytest.raises(U.UavqError) as e:
         U.Plan([q] * n, list(range(n)), 2, 4000, 200.0, 0.5, 1, inst_T=sch)
     assert e.value.code == U.ETOOBIG
+
+
+def test_pt_batch_argument_errors(U):
+    q = U.qubo_build(3, 3)
+    with pytest.raises(ValueError):
+        U.ParallelTemperingBatch([q, q], [0, 2], 4, 8, 10, 50.0, 1.0)   # id ranges 0..3 and 2..5 overlap
+    L = U.lib()
+    p = C.c_void_p(8)
+    assert L.uavq_pt_exchange_batch(0, 4, 8, 0, 1, p, p, p, p, p, 2, p, p, None, None) == U.EINVAL
+    assert L.uavq_pt_exchange_batch(2, 4, 8, 0, 1, None, p, p, p, p, 2, p, p, None, None) == U.EINVAL
+    assert L.uavq_pt_exchange_batch(2, 1, 8, 0, 1, p, p, p, p, p, 2, p, p, None, None) == 0   # K = 1: no pairs

@@ -181,3 +181,29 @@ def test_tempering_plan_options_equal_default(U, kw):
     for f in ("states", "E", "best_E", "best_sweep", "best_states", "accepts", "draws", "inst_best_E", "swaps"):
         assert torch.equal(got[f], ref[f]), (kw, f)
     assert got["rounds"] == ref["rounds"]
+
+
+def test_batch_equals_single_fields(U, oracle_lib):
+    """A batch of fields of different sizes in one plan, one batched exchange
+    launch per round: every field's outputs equal its own tempering run bit
+    for bit, and one of them equals the oracle's per-chain loop."""
+    import torch
+    gs = [inputs.grid(5, 6, 0.0, seed=7, inst=100), inputs.grid(8, 8, 0.1, seed=7, inst=200),
+          inputs.grid(9, 9, 0.1, seed=7, inst=300)]
+    K, R, S, iv = 4, 24, 30, 2
+    say(f"case: tempering batch of {len(gs)} fields K={K} R={R} S={S}")
+    qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in gs]
+    batch = U.ParallelTemperingBatch(qs, [g.inst_id for g in gs], K, R, S, 90.0, 1.5, seed=3, interval=iv).run()
+    torch.cuda.synchronize()
+    for i, (g, q) in enumerate(zip(gs, qs)):
+        one = U.ParallelTempering(q, g.inst_id, K, R, S, 90.0, 1.5, seed=3, interval=iv).run()
+        torch.cuda.synchronize()
+        for f in ("states", "E", "best_E", "best_sweep", "best_states", "accepts", "draws", "inst_best_E", "swaps"):
+            assert torch.equal(batch[i][f], one[f]), (i, f)
+        assert batch[i]["rounds"] == one["rounds"]
+    g, q = gs[1], qs[1]
+    o = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly)
+    ref = oracle_lib.pt_anneal_chains(o, K, list(range(R)), S, 90.0, 1.5, 3, g.inst_id, interval=iv, threads=8)
+    assert np.array_equal(batch[1]["E"].cpu().numpy(), ref["final_E"].T)
+    assert np.array_equal(batch[1]["best_E"].cpu().numpy(), ref["best_E"].T)
+    assert np.array_equal(batch[1]["swaps"].cpu().numpy().astype(np.uint64), ref["swaps"].sum(0))
