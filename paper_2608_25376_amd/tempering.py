@@ -92,6 +92,56 @@ def batch_study(n, K, R, sweeps, T_hot, T_cold, seed, interval):
             "batch_ms": batch_ms, "per_field_ms": single_ms, "identical": bool(same)}
 
 
+def ttt_study(n, K, R, ladder, T_hot, T_cold, seed, interval, ref_sweeps, T_const=0.0):
+    """Time to target on the warm-start study's held-out fields (n fields of
+    10x10, ids from 20000): for each sweep budget S of the ladder, the plain
+    annealer (K*R replicas per field, T_hot -> T_cold, one persistent launch for
+    all fields) and batched tempering (K slots x R chains per field, exchanges
+    every `interval` sweeps); a field is at target when its best energy is
+    within 1% of the best any run found (a plain reference run of ref_sweeps
+    included).  With T_const > 0 the plain annealer also runs at that constant
+    temperature.  Reports the fraction at target per budget and the time of
+    the ladder up to the largest first budget at target."""
+    from paper_2608_25376_amd import warmstart
+    grids = warmstart.make_instances(n, 20000)
+    qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in grids]
+    _, ref, _ = warmstart._anneal(qs, grids, K * R, ref_sweeps, T_hot, T_cold, seed + 1000)
+    best = ref.inst_best_E.cpu().numpy().copy()
+    runs = {}
+    for S in ladder:
+        _, out, ms = warmstart._anneal(qs, grids, K * R, S, T_hot, T_cold, seed)
+        runs[("plain", S)] = (out.inst_best_E.cpu().numpy().copy(), ms)
+        bt = _tempering_batch_best(qs, grids, K, R, S, T_hot, T_cold, seed, interval)
+        runs[("tempering", S)] = bt
+        if T_const > 0:
+            _, out, ms = warmstart._anneal(qs, grids, K * R, S, T_const, T_const, seed)
+            runs[("constant", S)] = (out.inst_best_E.cpu().numpy().copy(), ms)
+    for v in runs.values():
+        best = np.minimum(best, v[0])
+    hit = lambda E: 100 * E <= 101 * best
+    rep = {"fields": n, "K": K, "R": R, "ladder": list(ladder), "T_hot": T_hot, "T_cold": T_cold,
+           "interval": interval, "ref_sweeps": ref_sweeps, "T_const": T_const, "modes": {}}
+    for mode in ("plain", "tempering") + (("constant",) if T_const > 0 else ()):
+        frac = {S: float(hit(runs[(mode, S)][0]).mean()) for S in ladder}
+        gap = {S: float(np.mean(runs[(mode, S)][0] / best - 1.0)) for S in ladder}
+        firsts = [next((S for S in ladder if hit(runs[(mode, S)][0])[i]), None) for i in range(n)]
+        reached = [S for S in firsts if S is not None]
+        s_last = max(reached) if reached else None
+        ladder_ms = sum(runs[(mode, S)][1] for S in ladder if s_last is not None and S <= s_last)
+        rep["modes"][mode] = {"fraction_at_target": frac, "mean_gap": gap, "solved": len(reached),
+                              "ladder_ms_to_all_first_hits": ladder_ms,
+                              "ms_per_S": {S: runs[(mode, S)][1] for S in ladder}}
+    return rep
+
+
+def _tempering_batch_best(qs, grids, K, R, S, T_hot, T_cold, seed, interval):
+    """(per-field best energy over all slots, ms) of one batched tempering run."""
+    ids = [g.inst_id * K for g in grids]          # disjoint id ranges of K slots
+    bt = uavq.ParallelTemperingBatch(qs, ids, K, R, S, T_hot, T_cold, seed=seed, interval=interval)
+    res, ms = _timed(bt.run)
+    return np.array([int(r["inst_best_E"].min().cpu()) for r in res], np.int64), ms
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--K", type=int, default=16)
@@ -106,10 +156,23 @@ def main():
                          "tempering with an exchange every 10 sweeps); 0 = skip")
     ap.add_argument("--fields", default="")
     ap.add_argument("--batch", type=int, default=0, help="only the batch study: this many fields in one plan")
+    ap.add_argument("--ttt", type=int, default=0, help="only the time-to-target study on this many held-out fields")
+    ap.add_argument("--ladder", default="50,100,200,400,800,1600,3200")
+    ap.add_argument("--T-const", type=float, default=0.0, help="time-to-target study: also a plain run at this "
+                    "constant temperature")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
     import torch
     assert torch.cuda.is_available()
+    if args.ttt:
+        ladder = [int(v) for v in args.ladder.split(",")]
+        iv = int(args.intervals.split(",")[-1])
+        rep = ttt_study(args.ttt, args.K, args.R, ladder, args.T_hot, args.T_cold, 1, iv, 8000, args.T_const)
+        print(json.dumps(rep), flush=True)
+        if args.out:
+            with open(args.out, "w") as f:
+                f.write(json.dumps(rep) + "\n")
+        return
     if args.batch:
         q0 = uavq.qubo_build(3, 3)
         tempering(q0, 0, 2, 8, 4, 10.0, 1.0, 1, 1)     # load the kernels before timing
