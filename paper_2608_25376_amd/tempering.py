@@ -118,9 +118,21 @@ def ttt_study(n, K, R, ladder, T_hot, T_cold, seed, interval, ref_sweeps, T_cons
             runs[("constant", S)] = (out.inst_best_E.cpu().numpy().copy(), ms)
     for v in runs.values():
         best = np.minimum(best, v[0])
+    stop = None
+    if T_const > 0:
+        # the constant-temperature runs freeze early: the same anneal with UAVQ_STOP_FROZEN at the largest budget
+        S = ladder[-1]
+        plan = uavq.Plan(qs, [g.inst_id for g in grids], K * R, S, T_const, T_const, seed, persistent=True,
+                         stop_frozen=True)
+        plan.upload()
+        out = plan.alloc_outputs()
+        _, ms = _timed(lambda: plan.anneal(out=out))
+        stop = {"sweeps": S, "ms": ms,
+                "identical": bool(np.array_equal(out.inst_best_E.cpu().numpy(), runs[("constant", S)][0]))}
     hit = lambda E: 100 * E <= 101 * best
     rep = {"fields": n, "K": K, "R": R, "ladder": list(ladder), "T_hot": T_hot, "T_cold": T_cold,
-           "interval": interval, "ref_sweeps": ref_sweeps, "T_const": T_const, "modes": {}}
+           "interval": interval, "ref_sweeps": ref_sweeps, "T_const": T_const, "constant_stop_frozen": stop,
+           "modes": {}}
     for mode in ("plain", "tempering") + (("constant",) if T_const > 0 else ()):
         frac = {S: float(hit(runs[(mode, S)][0]).mean()) for S in ladder}
         gap = {S: float(np.mean(runs[(mode, S)][0] / best - 1.0)) for S in ladder}
