@@ -4,8 +4,9 @@ One step = one full anneal_batch of the workload (replica initialisation,
 all sweeps, per-instance reduction) with the plan's static data already
 resident in HBM.  Prints one JSON line.
 
-Default workload: 8x8 field with Bernoulli(0.1) no-fly cells (54 free cells,
-2916 variables), 1024 replicas, 2000 sweeps, geometric T 200 -> 0.5, seed 1.
+Default workload: 12x12 field, no obstacles (143 free cells, 20449
+variables), 4096 replicas, 4000 sweeps, geometric T 200 -> 0.5, seed 1 --
+the largest single-GPU configuration of the hot path.
 """
 import argparse
 import hashlib
@@ -36,7 +37,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="grid8x8_nofly0.1")
+    ap.add_argument("--workload", default="grid12x12")
     ap.add_argument("--kernel", default="factored", choices=["factored", "dense"])
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--rowmask", action="store_true", help="m <= 64: rebuild travel rows from step masks")
@@ -218,28 +219,45 @@ def copy_calibration(nbytes):
     print(json.dumps({"copy_bytes": nbytes, "read_bytes": nbytes, "write_bytes": nbytes}), flush=True)
 
 
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(w, q_gpu_m, args):
-    """The oracle as it stands, on a bounded sample of the same workload."""
-    import numpy as np
+    """The oracle as it stands, on a bounded sample of the same workload: one
+    replica on one thread (the single-thread rate), then a sample sized for
+    about 15 s on all threads."""
     import oracle
     g = w.grids[0]
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-    o = oracle.OracleQubo(g.rows, g.cols, nofly=g.nofly)
+    # large fields: the oracle evaluates each coefficient of J from its definition
+    o = oracle.OracleQubo(g.rows, g.cols, nofly=g.nofly, dense=len(g.nofly) <= 100)
     table = oracle.thresholds(w.T0, w.T1, w.sweeps)
-    # calibrate: one replica, then size the sample for ~15 s of work
+    t0 = time.perf_counter()
+    oracle.anneal(o, w.sweeps, w.T0, w.T1, w.seed, g.inst_id, [0], table=table, threads=1)
+    one = time.perf_counter() - t0
     reps = args.cpu_replicas
     if reps <= 0:
-        t0 = time.perf_counter()
-        oracle.anneal(o, w.sweeps, w.T0, w.T1, w.seed, g.inst_id, [0], table=table, threads=1)
-        one = time.perf_counter() - t0
         reps = int(max(threads, min(w.replicas, round(15.0 * threads / max(one, 1e-3)))))
     t0 = time.perf_counter()
     oracle.anneal(o, w.sweeps, w.T0, w.T1, w.seed, g.inst_id, list(range(reps)), table=table, threads=threads)
     dt = time.perf_counter() - t0
     attempts = reps * w.sweeps * o.N
     return {"value": attempts / dt, "unit": "attempts/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "logical_cpus": os.cpu_count(),
+            "single_thread_value": w.sweeps * o.N / one,
             "sample": f"{reps} of {w.replicas} replicas x {w.sweeps} sweeps of the same instance "
-                      f"({attempts:.3g} attempts, {dt:.1f} s)"}
+                      f"({attempts:.3g} attempts, {dt:.1f} s on {threads} threads; single thread: replica 0, "
+                      f"{w.sweeps * o.N:.3g} attempts, {one:.1f} s)"}
 
 
 def main():

@@ -16,8 +16,14 @@
  *     On failure no output buffer is written unless stated otherwise.
  *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
  *     device memory owned by the caller (the library never frees them).
- *   - Handles (uavq_qubo, uavq_plan) are created and freed by the library and
- *     are immutable after creation; they may be shared between threads.
+ *   - Handles (uavq_qubo, uavq_plan) are created and freed by the library.  A
+ *     qubo is immutable.  A plan's only state after creation is a cache filled
+ *     on first use (the launch shape, which needs the device, and in
+ *     UAVQ_GRAPH mode the captured graph), guarded by a per-plan lock: both
+ *     handles may be shared between threads (graph-mode launches of one plan
+ *     are serialised by that lock; a call with other buffers or another
+ *     stream re-captures).  uavq_plan_set_timing / uavq_plan_sweep_ms are the
+ *     exception: not thread-safe per plan.
  *   - Streams are hipStream_t passed as void*; NULL is the default stream.
  *     uavq_anneal_batch and uavq_energy_eval_dev are asynchronous on it.
  *
@@ -93,8 +99,10 @@ typedef struct {
  * (s = start cell).  The handle keeps the free list, the cost matrix D
  * (m x m) and the start-cell costs, and the dense J when UAVQ_DENSE is set.
  * Errors: EINVAL for a bad grid (no free cell, start cell no-fly, penalty <=
- * w_max, rows*cols > 65536), ETOOBIG when w_max > 255 (D is stored as bytes)
- * or, with UAVQ_DENSE, when N > 46340 or 2P > 32767. */
+ * w_max, rows*cols > 65536) or a penalty too large for int32 fields (P >
+ * 2^20, or 2P (3m + 2) + 2 m w_max >= 2^30); ETOOBIG when w_max > 255 (D is
+ * stored as bytes) or, with UAVQ_DENSE, when N > 46340 or 2P + w_max > 16383
+ * (the dense J splits into two int8 limbs). */
 int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out);
 void uavq_qubo_free(uavq_qubo *q);
 int uavq_qubo_info(const uavq_qubo *q, uavq_qubo_info_t *info);

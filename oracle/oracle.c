@@ -482,23 +482,29 @@ int32_t orc_tour_brute(int32_t m, const int32_t *W, int32_t closed, int64_t *bes
 }
 
 /* Held-Karp dynamic programme (textbook): best[S][j] = cheapest path from the
- * depot through the set S of free cells ending at j.  m <= 20. */
+ * depot through the set S of free cells ending at j.  m <= 24; a path has at
+ * most 25 legs of at most 2^24 each here, so the table holds int32 (1.6 GB at
+ * m = 24).  Returns -1 if m is out of range or the table cannot be allocated. */
 int64_t orc_held_karp(int32_t m, const int32_t *W, int32_t closed)
 {
-    if (m < 1 || m > 20) return -1;
+    if (m < 1 || m > 24) return -1;
+    for (int32_t i = 0; i < (m + 1) * (m + 1); i++)
+        if (W[i] < 0 || W[i] >= (1 << 24)) return -1;
+    const int32_t INF = INT32_MAX;
     uint32_t full = (1u << m);
-    int64_t *dp = (int64_t *)malloc(sizeof(int64_t) * (size_t)full * (size_t)m);
-    for (uint64_t i = 0; i < (uint64_t)full * m; i++) dp[i] = INT64_MAX;
+    int32_t *dp = (int32_t *)malloc(sizeof(int32_t) * (size_t)full * (size_t)m);
+    if (!dp) return -1;
+    for (uint64_t i = 0; i < (uint64_t)full * m; i++) dp[i] = INF;
     for (int32_t j = 0; j < m; j++) dp[(1u << j) * (uint64_t)m + j] = W[0 * (m + 1) + (j + 1)];
     for (uint32_t set = 1; set < full; set++) {
         for (int32_t j = 0; j < m; j++) {
             if (!(set & (1u << j))) continue;
-            int64_t cur = dp[(uint64_t)set * m + j];
-            if (cur == INT64_MAX) continue;
+            int32_t cur = dp[(uint64_t)set * m + j];
+            if (cur == INF) continue;
             for (int32_t k = 0; k < m; k++) {
                 if (set & (1u << k)) continue;
                 uint32_t ns = set | (1u << k);
-                int64_t v = cur + W[(j + 1) * (m + 1) + (k + 1)];
+                int32_t v = cur + W[(j + 1) * (m + 1) + (k + 1)];
                 if (v < dp[(uint64_t)ns * m + k]) dp[(uint64_t)ns * m + k] = v;
             }
         }

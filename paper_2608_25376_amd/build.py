@@ -45,7 +45,7 @@ def build(force: bool = True, verbose: bool = False) -> str:
     # chunks (m <= 384), or the lane's arrays move to scratch memory; the other
     # kernels of the file compile to the same code with or without this.
     per_file = {"uavq_kernels.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
-    objs = []
+    objs, cmds = [], []
     for s in SOURCES:
         src = os.path.join(CSRC, s)
         obj = os.path.join(objdir, os.path.splitext(s)[0] + ".o")
@@ -55,8 +55,14 @@ def build(force: bool = True, verbose: bool = False) -> str:
             cmd = [hipcc, "-x", "c++"] + common + ["-c", src, "-o", obj]
         if verbose:
             print(" ".join(cmd))
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    # the sources compile independently: one compiler process each
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=min(len(cmds), 8)) as ex:
+        for r in list(ex.map(lambda c: subprocess.run(c), cmds)):
+            if r.returncode != 0:
+                raise subprocess.CalledProcessError(r.returncode, r.args)
     tmp = LIB + ".tmp"
     subprocess.run([hipcc, "-shared", "--offload-arch=" + ARCH, "-o", tmp] + objs, check=True)
     os.replace(tmp, LIB)

@@ -114,7 +114,13 @@ int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out) {
     if (wmax > 255) { delete q; return set_error(UAVQ_ETOOBIG, "qubo_build: w_max %d > 255", wmax); }
     int32_t P = g->penalty ? g->penalty : 2 * wmax;
     if (P <= wmax) { delete q; return set_error(UAVQ_EINVAL, "qubo_build: penalty %d <= w_max %d", P, wmax); }
-    if (P > (1 << 20)) { delete q; return set_error(UAVQ_EINVAL, "qubo_build: penalty too large"); }
+    // Every local field and energy change the kernels form is an int32: with
+    // R_t, C_c <= m and travel rows <= m w_max, |h| + |k 2P| stays below
+    // 2P (3m + 2) + 2 m w_max, kept under 2^30 (and 2P within 24 bits).
+    if (P > (1 << 20) || 2LL * P * (3LL * m + 2) + 2LL * m * wmax >= (1LL << 30)) {
+        delete q;
+        return set_error(UAVQ_EINVAL, "qubo_build: penalty %d too large for m = %d", P, m);
+    }
     q->P = P;
     q->c0 = 2LL * P * m;
     q->D.resize((size_t)m * m);
@@ -132,7 +138,8 @@ int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out) {
             q->b[(size_t)(t - 1) * m + c] = v;
         }
     if (g->flags & UAVQ_DENSE) {
-        if (q->N > 46340 || 2 * P + 255 > 32767) {
+        // J <= 2P + w_max must split into two int8 limbs (J & 127, J >> 7 <= 127)
+        if (q->N > 46340 || 2 * P + wmax > 16383) {
             delete q;
             return set_error(UAVQ_ETOOBIG, "qubo_build: dense J too large (N=%d, P=%d)", m * m, P);
         }

@@ -1,6 +1,7 @@
 // Internal structures shared by the host code and the HIP kernels of libuavq.
 #pragma once
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -114,6 +115,9 @@ struct uavq_plan {
     int32_t timing = 0;                   // record events around the sweep launches
     void *ev[2 * (uavq::kMaxChunks + 1)] = {};
     int32_t persistent = 0, graph = 0;
+    // Caches filled on first use (launch shape, captured graph) are guarded by
+    // mu, so that one plan may be used from several threads.
+    std::mutex mu;
     int32_t prepared = 0, cu_count = 0;
     int32_t max_blocks[uavq::kMaxChunks + 2] = {};   // resident blocks per CU of each class's kernel
     size_t lds_class[uavq::kMaxChunks + 2] = {};

@@ -321,7 +321,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
         bestE = a.best_E[grep];
         bestS = a.best_sweep[grep];
     }
-    int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
+    int64_t Elane = 0;         // energy change of the lane's accepted flips in the current sweep
     uint32_t ndraw_lane = 0;   // draws of the lane's sites
     bool frozen = false;       // stop_frozen: a sweep had neither an accept nor a draw
     int dep[NJ];   // start-cell costs of this lane's cells (the fixed rows 0 and m+1)
@@ -502,7 +502,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
                             const int dEv = dE0[j] + __mul24(na - nr, dplus(j));
                             ndraw_lane += (64 * j + L < m && (uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)) ? 1u : 0u;
                             const int inA = (int)((accd[j] >> L) & 1ull);
-                            Elane += __mul24(inA, dEv);
+                            Elane += inA ? dEv : 0;   // |dEv| may exceed 24 bits for large penalties
                             Cc[j] += Ops::bit(mc, j, L) ? -inA : inA;
                             Yc[j] += dY[j];
                             nab += (int)__popcll(adds);
@@ -531,7 +531,7 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
             nacc += nacc_s;
             if (STOP && nacc_s == 0 && !ballot64(ndraw_lane != ndl0)) frozen = true;
             if (nacc_s) {
-                E += wave_sum64((int64_t)Elane);
+                E += wave_sum64(Elane);
                 Elane = 0;
             }
             if (E < bestE) {
@@ -799,7 +799,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
         bestE = a.best_E[grep];
         bestS = a.best_sweep[grep];
     }
-    int Elane = 0;             // energy change of the lane's accepted flips in the current sweep
+    int64_t Elane = 0;         // energy change of the lane's accepted flips in the current sweep
     uint32_t ndraw_lane = 0;   // draws of the lane's sites visited by the sequential walk
     bool frozen = false;       // stop_frozen: a sweep had neither an accept nor a draw
 
@@ -1025,7 +1025,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                             const int inA = (int)((accd >> L) & 1ull);   // this lane's site was flipped
                             cm ^= (uint64_t)inA << (t - 1);
                             Kc += __mul24(inA, dplus);
-                            Elane += __mul24(inA, dEv);
+                            Elane += inA ? dEv : 0;   // |dEv| may exceed 24 bits for large penalties
                             Yv[i + 1] += dY;
                         }
                     }
@@ -1046,7 +1046,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
             if (PC && L == 0) pc_drew[2 * slot + (s & 1)] = drew ? 1 : 0;
             if (STOP && nacc_s == 0 && !drew) frozen = true;
             if (nacc_s) {
-                E += wave_sum64((int64_t)Elane);
+                E += wave_sum64(Elane);
                 Elane = 0;
             }
             if (E < bestE) {
@@ -1250,6 +1250,7 @@ static const void *class_kernel(const uavq_plan *pl, int cls) {
 // capture: dynamic LDS limits and, for persistent launches, resident blocks.
 static int prepare(const uavq_plan *cpl) {
     uavq_plan *pl = const_cast<uavq_plan *>(cpl);
+    std::lock_guard<std::mutex> lock(pl->mu);   // the only writer of these fields after creation
     if (pl->prepared) return UAVQ_OK;
     int dev = 0;
     UAVQ_HIP(hipGetDevice(&dev));
@@ -1466,8 +1467,10 @@ int uavq_anneal_segment(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const 
     a.inst_state_off = (int64_t *)(ws + pl->inst_state_off_off);
     if (!pl->graph) return launch_anneal(pl, a, stream, out->check_E);
 
-    // graph mode: replay the captured sequence while every pointer is unchanged
+    // graph mode: replay the captured sequence while every pointer is unchanged;
+    // the cached graph is shared, so capture and launch hold the plan's lock
     uavq_plan *mp = const_cast<uavq_plan *>(pl);
+    std::lock_guard<std::mutex> lock(mp->mu);
     uint64_t key = 0x12345678ull;
     const void *ptrs[] = {d_ws, stream, a.init_states, a.seeded, a.start_sweep, out->final_states, out->final_E,
                           out->best_E, out->best_sweep, out->best_states, out->accepts, out->draws, out->inst_best_E,

@@ -12,10 +12,10 @@ def say(msg):
 
 def gpu_anneal(U, grids, R, S, T0, T1, seed=1, dense=False, wpb=0, closed=True, init_x=None, seeded=None,
                start_sweep=None, check_E=False, rowmask=False, persistent=False, graph=False, tune=None,
-               stream=None, replays=1, no_producer=False, stop_frozen=False):
+               stream=None, replays=1, no_producer=False, stop_frozen=False, penalty=0):
     """Anneal ``grids`` (inputs.Grid list) on cuda:0; returns (qubos, plan, numpy results)."""
     import torch
-    qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly, closed=closed, dense=dense) for g in grids]
+    qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly, closed=closed, dense=dense, penalty=penalty) for g in grids]
     plan = U.Plan(qs, [g.inst_id for g in grids], R, S, T0, T1, seed, dense=dense, waves_per_block=wpb,
                   rowmask=rowmask, persistent=persistent, graph=graph, tune=tune, no_producer=no_producer,
                   stop_frozen=stop_frozen)
@@ -79,3 +79,14 @@ def compare_replicas(gpu, orc, reps, label=""):
             bad = np.nonzero((g != o).reshape(len(reps), -1).any(1))[0]
             raise AssertionError(f"{label}: field {f} differs for replicas {[reps[i] for i in bad[:8]]}: "
                                  f"gpu {g.reshape(len(reps), -1)[bad[0]][:12]} oracle {o.reshape(len(reps), -1)[bad[0]][:12]}")
+
+
+def check_reduce(oracle, gi, R, label=""):
+    """The per-instance outputs equal the oracle's lexicographic minimum of
+    (best_E, replica) taken over the GPU's own per-replica results (every
+    replica, whether or not the oracle re-ran it)."""
+    best = oracle.instance_best(gi, list(range(R)))
+    assert gi["inst_best_E"] == best["best_E"], label
+    assert gi["inst_best_replica"] == best["best_replica"], label
+    assert gi["inst_best_sweep"] == best["best_sweep"], label
+    assert (gi["inst_best_x"] == best["best_x"]).all(), label

@@ -107,6 +107,24 @@ def test_validation_errors(U):
         U.qubo_build(2, 2, nofly=nf)             # start cell no-fly
     with pytest.raises(U.UavqError):
         U.qubo_build(2, 2, penalty=14)           # penalty must exceed w_max
+    # int32 fields: P <= 2^20 and 2P(3m + 2) + 2 m w_max < 2^30
+    assert U.qubo_build(8, 8, penalty=1 << 20).P == 1 << 20
+    with pytest.raises(U.UavqError) as e:
+        U.qubo_build(8, 8, penalty=(1 << 20) + 1)
+    assert e.value.code == U.EINVAL
+    big = U.qubo_build(19, 19)                   # m = 360, w_max = 255
+    lim = ((1 << 30) - 2 * 360 * 255 - 1) // (2 * (3 * 360 + 2))
+    assert U.qubo_build(19, 19, penalty=lim).P == lim
+    with pytest.raises(U.UavqError):
+        U.qubo_build(19, 19, penalty=lim + 1)
+    assert big.m == 360
+    # dense J: 2P + w_max <= 16383 (two int8 limbs)
+    w7 = U.qubo_build(7, 7).w_max
+    Pd = (16383 - w7) // 2
+    assert U.qubo_build(7, 7, penalty=Pd, dense=True).P == Pd
+    with pytest.raises(U.UavqError) as e:
+        U.qubo_build(7, 7, penalty=Pd + 1, dense=True)
+    assert e.value.code == U.ETOOBIG
     with pytest.raises(U.UavqError) as e:
         U.qubo_build(30, 30)                     # w_max > 255
     assert e.value.code == U.ETOOBIG
@@ -256,3 +274,32 @@ def test_pt_batch_argument_errors(U):
     assert L.uavq_pt_exchange_batch(0, 4, 8, 0, 1, p, p, p, p, p, 2, p, p, None, None) == U.EINVAL
     assert L.uavq_pt_exchange_batch(2, 4, 8, 0, 1, None, p, p, p, p, 2, p, p, None, None) == U.EINVAL
     assert L.uavq_pt_exchange_batch(2, 1, 8, 0, 1, p, p, p, p, p, 2, p, p, None, None) == 0   # K = 1: no pairs
+
+
+def test_plan_shared_between_threads(U):
+    """A plan may be used from several threads: the first-use cache (launch
+    shape) is filled under the plan's lock.  Without a GPU every thread gets
+    the same error back; no thread crashes or sees a half-filled plan."""
+    import threading
+    q = U.qubo_build(12, 12)
+    p = U.Plan([q, U.qubo_build(5, 5)], [0, 1], 8, 10, 50.0, 0.5)
+    results, errors = [], []
+
+    def work():
+        try:
+            for _ in range(50):
+                results.append(p.kernel_name(3))
+        except Exception as ex:   # noqa: BLE001 - recorded and compared below
+            errors.append(type(ex).__name__ + ": " + str(ex).split(":")[0])
+
+    ts = [threading.Thread(target=work) for _ in range(8)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    # either every call succeeded with one answer (a GPU is present) or every
+    # thread failed the same way (no device to decide the launch shape on)
+    if results:
+        assert not errors and len(set(results)) == 1 and len(results) == 400
+    else:
+        assert len(errors) == 8 and len(set(errors)) == 1

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from paper_2608_25376_amd import inputs
-from tests.gpu_util import compare_replicas, gpu_anneal, say, split
+from tests.gpu_util import check_reduce, compare_replicas, gpu_anneal, say, split
 
 pytestmark = pytest.mark.gpu
 
@@ -30,9 +30,10 @@ def U():
 def test_batch256_full_size_persistent_graph(U, oracle_lib):
     """256 instances (side 4..10, no-fly density 0..0.2), 256 replicas, 2000
     sweeps, persistent kernels captured in a HIP graph.  Per instance the
-    oracle re-runs a sampled replica; for three instances it runs all 256
-    replicas and the per-instance best (energy, replica, sweep, state) must
-    match exactly."""
+    oracle re-runs a sampled replica, and the per-instance reduce over all 256
+    replicas is checked for every instance; for three instances the oracle
+    runs all 256 replicas and the per-instance best (energy, replica, sweep,
+    state) must match exactly."""
     import torch
     w = inputs.workload("batch256")
     stream = torch.cuda.Stream()
@@ -46,6 +47,7 @@ def test_batch256_full_size_persistent_graph(U, oracle_lib):
         r = int(rng.integers(0, w.replicas))
         orc = oracle_lib.anneal(o, w.sweeps, w.T0, w.T1, w.seed, g.inst_id, [r], threads=16)
         compare_replicas(per[i], orc, [r], f"batch256 instance {i} replica {r}")
+        check_reduce(oracle_lib, per[i], w.replicas, f"batch256 instance {i} reduce")
     ms = [q.m for q in qs]
     for i in (int(np.argmin(ms)), 17, 101):
         g = w.grids[i]

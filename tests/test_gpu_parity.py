@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2608_25376_amd import inputs
-from tests.gpu_util import compare_replicas, gpu_anneal, say, split
+from tests.gpu_util import check_reduce, compare_replicas, gpu_anneal, say, split
 
 pytestmark = pytest.mark.gpu
 
@@ -21,20 +21,26 @@ def U():
     return uavq
 
 
-def _oracle_for(oracle_lib, g, closed=True):
-    return oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed)
+def _oracle_for(oracle_lib, g, closed=True, penalty=0):
+    return oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, closed=closed, penalty=penalty,
+                                 dense=g.rows * g.cols <= 100)
 
 
 def _check_instance(U, oracle_lib, g, R, S, T0, T1, seed, reps=None, closed=True, wpb=0, dense=False,
-                    rowmask=False):
+                    rowmask=False, penalty=0, check_E=False, threads=8):
     say(f"case: {g.rows}x{g.cols} n_free={g.n_free} inst={g.inst_id} R={R} S={S} T={T0}->{T1} seed={seed} "
-        f"closed={closed} wpb={wpb} dense={dense} rowmask={rowmask}")
-    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, seed, dense=dense, wpb=wpb, closed=closed, rowmask=rowmask)
+        f"closed={closed} wpb={wpb} dense={dense} rowmask={rowmask} penalty={penalty}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, seed, dense=dense, wpb=wpb, closed=closed, rowmask=rowmask,
+                               penalty=penalty, check_E=check_E)
     gi = split(U, qs, plan, res)[0]
-    o = _oracle_for(oracle_lib, g, closed)
+    if check_E:
+        assert np.array_equal(gi["check_E"], gi["final_E"])
+    o = _oracle_for(oracle_lib, g, closed, penalty)
     reps = list(range(R)) if reps is None else list(reps)
-    orc = oracle_lib.anneal(o, S, T0, T1, seed, g.inst_id, reps, threads=8)
+    orc = oracle_lib.anneal(o, S, T0, T1, seed, g.inst_id, reps, threads=threads)
     compare_replicas(gi, orc, reps, f"{g.rows}x{g.cols}")
+    # the reduce over every replica (those the oracle did not re-run included)
+    check_reduce(oracle_lib, gi, R, f"{g.rows}x{g.cols} reduce")
     if len(reps) == R:
         best = oracle_lib.instance_best(orc, reps)
         assert gi["inst_best_E"] == best["best_E"]
@@ -280,20 +286,41 @@ def test_determinism(U):
         assert np.array_equal(a[k], b[k]), k
 
 
-def test_grid8x8_full_size_sampled(U, oracle_lib):
-    """The benchmark workload (8x8, no-fly 0.1, 1024 replicas, 2000 sweeps,
-    T 200 -> 0.5) in the benchmark's launch configuration; the oracle
-    recomputes a sample of replicas one by one."""
+def test_grid8x8_full_size_all_replicas(U, oracle_lib):
+    """The 8x8 workload (no-fly 0.1, 1024 replicas, 2000 sweeps, T 200 ->
+    0.5) in its default launch configuration: every replica against the
+    oracle, the per-instance best against the oracle's, and the MFMA energy of
+    every final state against the incrementally kept one."""
     w = inputs.workload("grid8x8_nofly0.1")
     g = w.grids[0]
-    _check_instance(U, oracle_lib, g, w.replicas, w.sweeps, w.T0, w.T1, w.seed, reps=[0, 1, 2, 511, 777, 1023])
+    _check_instance(U, oracle_lib, g, w.replicas, w.sweeps, w.T0, w.T1, w.seed, check_E=True, threads=16)
 
 
 def test_grid12x12_full_size_sampled(U, oracle_lib):
     """The 12x12 configuration (143 free cells, 20449 variables, 4096
-    replicas, 4000 sweeps, T 200 -> 0.5; three cell chunks per lane) at full
-    size; the oracle recomputes three replicas one by one."""
+    replicas, 4000 sweeps, T 200 -> 0.5) at full size, in the launch the
+    benchmark times: sixteen replicas spread over the grid of workgroups are
+    recomputed by the oracle one by one, the per-instance reduce over all 4096
+    replicas is checked, and every final state's MFMA energy equals the
+    incrementally kept one."""
     w = inputs.workload("grid12x12")
     g = w.grids[0]
     assert g.n_free == 143 and w.replicas == 4096 and w.sweeps == 4000
-    _check_instance(U, oracle_lib, g, w.replicas, w.sweeps, w.T0, w.T1, w.seed, reps=[0, 2049, 4095])
+    reps = [0, 1, 2, 3, 255, 256, 1023, 1024, 2047, 2049, 3000, 3071, 3333, 4092, 4094, 4095]
+    _check_instance(U, oracle_lib, g, w.replicas, w.sweeps, w.T0, w.T1, w.seed, reps=reps, check_E=True,
+                    threads=16)
+
+
+@pytest.mark.parametrize("rows,cols,dens,inst,R", [(6, 6, 0.1, 60, 24), (8, 8, 0.1, 0, 64), (10, 10, 0.1, 61, 16),
+                                                   (12, 12, 0.0, 62, 8)])
+def test_largest_penalty(U, oracle_lib, rows, cols, dens, inst, R):
+    """The largest penalty qubo_build accepts for these fields (P = 2^20):
+    energy changes far beyond 24 bits in the first sweeps (random states
+    break hundreds of one-hot constraints) follow the oracle bit for bit, on
+    the m <= 64 kernel and on the two- and three-chunk kernels."""
+    g = inputs.grid(rows, cols, dens, seed=3, inst=inst)
+    P = 1 << 20
+    gi, o = _check_instance(U, oracle_lib, g, R, 30, 200.0, 0.5, 17, penalty=P, check_E=True)
+    assert o.P == P
+    with pytest.raises(U.UavqError):
+        U.qubo_build(rows, cols, nofly=g.nofly, penalty=P + 1)

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 from paper_2608_25376_amd import inputs
-from tests.gpu_util import compare_replicas, gpu_anneal, say, split
+from tests.gpu_util import check_reduce, compare_replicas, gpu_anneal, say, split
 
 pytestmark = pytest.mark.gpu
 
@@ -79,19 +79,43 @@ def test_dense_kernel_matches_oracle(U, oracle_lib, rows, cols, dens, inst, clos
 
 
 def test_dense_equals_factored_grid8x8(U, oracle_lib):
-    """8x8 benchmark field (dense J int16, 2916 variables): dense kernel ==
-    factored kernel on every replica, and == oracle on sampled replicas."""
+    """The 8x8 workload at full size (dense J int16, 2916 variables, 1024
+    replicas x 2000 sweeps): dense kernel == factored kernel on every
+    replica, == oracle on sampled replicas, and its per-instance reduce over
+    all replicas == the oracle's over the same per-replica results."""
     w = inputs.workload("grid8x8_nofly0.1")
     g = w.grids[0]
-    R, S = 256, 400
+    R, S = w.replicas, w.sweeps
     say(f"case: dense vs factored 8x8 R={R} S={S}")
-    qd, pd, rd = gpu_anneal(U, [g], R, S, w.T0, w.T1, w.seed, dense=True)
+    qd, pd, rd = gpu_anneal(U, [g], R, S, w.T0, w.T1, w.seed, dense=True, check_E=True)
     qf, pf, rf = gpu_anneal(U, [g], R, S, w.T0, w.T1, w.seed)
     for k in ("final_states", "best_states", "final_E", "best_E", "best_sweep", "accepts", "draws", "inst_best_E",
               "inst_best_replica", "inst_best_state"):
         assert np.array_equal(rd[k], rf[k]), k
+    assert np.array_equal(rd["check_E"], rd["final_E"])
     gi = split(U, qd, pd, rd)[0]
     o = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly)
-    reps = [0, 77, 255]
+    reps = [0, 1, 77, 255, 256, 511, 640, 1023]
     orc = oracle_lib.anneal(o, S, w.T0, w.T1, w.seed, g.inst_id, reps, threads=8)
     compare_replicas(gi, orc, reps, "dense 8x8")
+    check_reduce(oracle_lib, gi, R, "dense 8x8 reduce")
+
+
+def test_dense_largest_penalty(U, oracle_lib):
+    """The largest penalty the dense J accepts (2P + w_max = 16383, so the high
+    int8 limb of J is 127): the MFMA field refresh and the dense sweep follow
+    the oracle bit for bit, and one more unit of penalty is refused."""
+    g = inputs.grid(7, 7, 0.1, seed=5, inst=70)
+    wmax = U.qubo_build(g.rows, g.cols, nofly=g.nofly).w_max
+    P = (16383 - wmax) // 2
+    say(f"case: dense 7x7 P={P}")
+    R, S, T0, T1 = 16, 40, 200.0, 0.5
+    qs, plan, res = gpu_anneal(U, [g], R, S, T0, T1, 23, dense=True, check_E=True, penalty=P)
+    gi = split(U, qs, plan, res)[0]
+    assert np.array_equal(res["check_E"], res["final_E"])
+    o = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, penalty=P)
+    orc = oracle_lib.anneal(o, S, T0, T1, 23, g.inst_id, list(range(R)), threads=8)
+    compare_replicas(gi, orc, list(range(R)), "dense largest penalty")
+    check_reduce(oracle_lib, gi, R, "dense largest penalty reduce")
+    with pytest.raises(U.UavqError):
+        U.qubo_build(g.rows, g.cols, nofly=g.nofly, penalty=P + 1, dense=True)

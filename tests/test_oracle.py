@@ -157,6 +157,20 @@ def test_3x3_optimum(oracle_lib):
     assert q.path_cost(g["optimal_tour_rowmajor"]) == g["optimum"]
 
 
+@pytest.mark.parametrize("rows,cols,closed,opt", [
+    (1, 25, True, 480),    # m = 24 on a line: out to the far end and back, 2 x 10 x 24
+    (3, 8, True, 240),     # m = 23: a Hamiltonian cycle of 24 unit legs exists on 3 x 8 (an even side)
+    (2, 11, False, 210),   # m = 21, open: a Hamiltonian path of 21 unit legs
+])
+def test_held_karp_closed_forms_up_to_24_cells(oracle_lib, rows, cols, closed, opt):
+    """Held-Karp at 21 to 24 free cells (int32 table) against optima that
+    follow from geometry: every leg costs at least 10, and the tours named
+    above use only unit legs (on the line, the return leg is one jump)."""
+    q = oracle_lib.OracleQubo(rows, cols, closed=closed, dense=False)
+    assert 21 <= q.m <= 24
+    assert q.held_karp() == opt
+
+
 def test_held_karp_equals_brute_force(oracle_lib):
     for i in range(8):
         g = inputs.grid(4, 4, 0.35, seed=21, inst=i)
