@@ -246,7 +246,10 @@ typedef struct {              /* device outputs, caller-owned; NULL = not wanted
  *     r, inst}, key {seed, 0}) and no draw is taken when that entry is 0;
  *   at each sweep end the state is kept as the replica's best if E < best_E.
  * Per instance the best is the lexicographic minimum of (best_E, replica).
- * Asynchronous on `stream`; outputs are valid once the stream has drained. */
+ * Asynchronous on `stream`; outputs are valid once the stream has drained.
+ * d_ws is read, and in persistent or dense mode also written (item counters,
+ * unpacked states and fields): launches that may overlap need a workspace
+ * each (uavq_plan_upload into every one). */
 int uavq_anneal_batch(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
                       const uavq_anneal_out *out, void *stream);
 

@@ -359,6 +359,9 @@ class Plan:
             self._h = None
 
     def upload(self, device="cuda", stream=None):
+        """A device workspace holding the plan's static data; kept as ``self.ws`` (the default
+        workspace of ``anneal``) and returned.  Launches that run at the same time need a
+        workspace each (persistent and dense launches write into theirs)."""
         import torch
         self.ws = torch.empty(max(self.ws_bytes, 1), dtype=torch.uint8, device=device)
         if stream is not None:
@@ -396,24 +399,25 @@ class Plan:
 
     def anneal(self, out: Optional[AnnealResult] = None, init_states=None, seeded=None, start_sweep=None,
                check_E=None, stream=None, s_begin: int = 0, s_end: Optional[int] = None,
-               resume: bool = False) -> AnnealResult:
+               resume: bool = False, ws=None) -> AnnealResult:
         """anneal_batch on this plan's workspace (asynchronous on ``stream``).  With a sweep range
         (anneal_segment) only sweeps s_begin .. s_end-1 of the schedule run; ``resume`` continues
         from what ``out`` holds (the outputs of a segment that ended at s_begin, or a restored
-        checkpoint)."""
-        if self.ws is None:
+        checkpoint).  ``ws``: another uploaded workspace of this plan (default: ``self.ws``)."""
+        ws = self.ws if ws is None else ws
+        if ws is None:
             raise RuntimeError("Plan.upload() must precede anneal()")
         if out is None:
             if resume:
                 raise ValueError("resume needs the outputs of the previous segment")
-            out = self.alloc_outputs(self.ws.device)
+            out = self.alloc_outputs(ws.device)
         init = _Init(_dptr(init_states), _dptr(seeded), _dptr(start_sweep))
         o = _Out(*[_dptr(getattr(out, f)) if f != "check_E" else _dptr(check_E) for f, _ in _Out._fields_])
         if s_begin == 0 and s_end is None and not resume:
-            _check(lib().uavq_anneal_batch(self._h, _dptr(self.ws), self.ws_bytes, C.byref(init), C.byref(o),
+            _check(lib().uavq_anneal_batch(self._h, _dptr(ws), self.ws_bytes, C.byref(init), C.byref(o),
                                            _stream_handle(stream)))
         else:
-            _check(lib().uavq_anneal_segment(self._h, _dptr(self.ws), self.ws_bytes, C.byref(init), C.byref(o),
+            _check(lib().uavq_anneal_segment(self._h, _dptr(ws), self.ws_bytes, C.byref(init), C.byref(o),
                                              int(s_begin), int(self.sweeps if s_end is None else s_end),
                                              1 if resume else 0, _stream_handle(stream)))
         return out
