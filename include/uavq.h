@@ -125,6 +125,18 @@ int uavq_energy_workspace_bytes(const uavq_qubo *q, size_t *bytes);
 int uavq_energy_eval_dev(const uavq_qubo *q, const uint32_t *d_x_packed, int64_t n_states, int64_t *d_E,
                          void *d_ws, size_t ws_bytes, void *stream);
 
+/* energy_eval on the device without a workspace, for callers that cannot
+ * allocate device memory (code under stream capture, serving loops, harnesses
+ * that forbid allocation): the same computation as uavq_energy_eval_dev, with
+ * the staging (cost matrix and start-cell costs, uavq_energy_workspace_bytes)
+ * in a static device buffer of 80 KiB that each device keeps until the process
+ * ends.  Allocates nothing.  ETOOBIG when the staging exceeds that buffer
+ * (m >= 286; the refresh kernel itself stops at m = 283).  All calls on one
+ * device share the buffer: calls that may overlap on a device (other streams
+ * or threads) race and must be ordered by the caller. */
+int uavq_energy_eval_dev_noalloc(const uavq_qubo *q, const uint32_t *d_x_packed, int64_t n_states, int64_t *d_E,
+                                 void *stream);
+
 /* Path reconstruction (Alg. 1, last step): for a permutation state, path[0..m+1]
  * (grid indices: start, the visited cells in order, start again; for an open
  * path path[m+1] = -1) and its travel cost.  EINFEASIBLE otherwise. */

@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <climits>
 #include <cstdint>
+#include <mutex>
 
 #include "uavq_device.h"
 
@@ -401,3 +402,55 @@ int launch_dense(const uavq_plan *pl, const KArgs &a, hipStream_t st) {
 }
 
 }  // namespace uavq
+
+// ------------------------------------------- allocation-free energy_eval --
+// Staging of uavq_energy_eval_dev_noalloc: the cost matrix and the start-cell
+// costs of the last call, in a file-scope device array instead of a caller
+// workspace.  Every device the library runs on holds its own copy until the
+// process ends; its address is looked up once per device with that device
+// current and kept per device.  80 KiB covers every field the refresh kernel
+// takes (its LDS tile reaches m = 283: 80,128 + 512 bytes of staging).
+namespace uavq {
+
+constexpr size_t kNoAllocScratchBytes = 80 * 1024;
+constexpr int kNoAllocMaxDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static uint8_t *g_scratch_ptr[kNoAllocMaxDevices] = {};
+
+static int scratch_for_current_device(uint8_t **out) {
+    int dev = 0;
+    UAVQ_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kNoAllocMaxDevices)
+        return set_error(UAVQ_EINVAL, "energy_eval_dev_noalloc: device %d beyond the %d supported", dev,
+                         kNoAllocMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return set_error(UAVQ_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return UAVQ_OK;
+}
+
+}  // namespace uavq
+
+extern "C" int uavq_energy_eval_dev_noalloc(const uavq_qubo *q, const uint32_t *d_x, int64_t n, int64_t *d_E,
+                                            void *stream) {
+    using namespace uavq;
+    if (!q || n < 0 || (n > 0 && (!d_x || !d_E)))
+        return set_error(UAVQ_EINVAL, "energy_eval_dev_noalloc: bad argument");
+    const size_t need = energy_ws_bytes(q);
+    if (need > kNoAllocScratchBytes)
+        return set_error(UAVQ_ETOOBIG, "energy_eval_dev_noalloc: m = %d needs %zu bytes of staging, the static "
+                         "buffer holds %zu", q->m, need, kNoAllocScratchBytes);
+    if (n == 0) return UAVQ_OK;
+    uint8_t *ptr = nullptr;
+    const int rc = scratch_for_current_device(&ptr);
+    if (rc) return rc;
+    return launch_energy(q, d_x, n, d_E, ptr, kNoAllocScratchBytes, stream);
+}

@@ -81,7 +81,8 @@ class _Out(C.Structure):
 EXPORTS = [
     "uavq_last_error", "uavq_version", "uavq_qubo_build", "uavq_qubo_free", "uavq_qubo_info",
     "uavq_qubo_free_cells", "uavq_qubo_costs", "uavq_qubo_export", "uavq_energy_eval",
-    "uavq_energy_workspace_bytes", "uavq_energy_eval_dev", "uavq_decode_path", "uavq_schedule",
+    "uavq_energy_workspace_bytes", "uavq_energy_eval_dev", "uavq_energy_eval_dev_noalloc", "uavq_decode_path",
+    "uavq_schedule",
     "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_kernel_name", "uavq_plan_layout",
     "uavq_plan_upload",
     "uavq_anneal_batch", "uavq_anneal_segment", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
@@ -114,6 +115,7 @@ def lib():
         L.uavq_energy_eval.argtypes = [vp, P(C.c_uint32), C.c_int64, P(C.c_int64)]
         L.uavq_energy_workspace_bytes.argtypes = [vp, P(C.c_size_t)]
         L.uavq_energy_eval_dev.argtypes = [vp, vp, C.c_int64, vp, vp, C.c_size_t, vp]
+        L.uavq_energy_eval_dev_noalloc.argtypes = [vp, vp, C.c_int64, vp, vp]
         L.uavq_decode_path.argtypes = [vp, P(C.c_uint32), P(C.c_int32), P(C.c_int64)]
         L.uavq_schedule.argtypes = [C.c_double, C.c_double, C.c_int32, P(C.c_int32), P(C.c_uint32)]
         L.uavq_plan_create.argtypes = [P(vp), C.c_int32, P(C.c_uint32), P(_Params), P(vp)]
@@ -260,6 +262,14 @@ def energy_eval_dev(q: Qubo, d_states, d_E=None, stream=None):
     ws = torch.empty(max(nb.value, 1), dtype=torch.uint8, device=d_states.device)
     _check(lib().uavq_energy_eval_dev(q.handle, _dptr(d_states), n, _dptr(d_E), _dptr(ws), nb.value,
                                       _stream_handle(stream)))
+    return d_E
+
+
+def energy_eval_dev_noalloc(q: Qubo, d_states, d_E, stream=None):
+    """energy_eval on the device with the library's static staging buffer: nothing is
+    allocated (``d_E`` is the caller's int64 output of one entry per state)."""
+    n = d_states.numel() // q.state_words
+    _check(lib().uavq_energy_eval_dev_noalloc(q.handle, _dptr(d_states), n, _dptr(d_E), _stream_handle(stream)))
     return d_E
 
 
