@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--rowmask", action="store_true", help="m <= 64: rebuild travel rows from step masks")
     ap.add_argument("--no-producer", action="store_true",
                     help="m <= 64 at one wave per SIMD: no cut-producing wave beside each replica")
+    ap.add_argument("--generic-chunk", action="store_true",
+                    help="64 < m <= 192: the generic chunked walk instead of the block-tested kernel")
     ap.add_argument("--persistent", action="store_true", help="persistent work-queue sweep kernels")
     ap.add_argument("--graph", action="store_true", help="replay anneal_batch as a captured HIP graph")
     ap.add_argument("--autotune", action="store_true", help="choose the launch shape with uavq_autotune")
@@ -291,7 +293,7 @@ def main():
     stream = torch.cuda.Stream() if args.graph else torch.cuda.current_stream()
     plan = uavq.Plan(qs, ids, w.replicas, w.sweeps, w.T0, w.T1, w.seed, dense=dense,
                      waves_per_block=args.waves_per_block, rowmask=args.rowmask, persistent=args.persistent,
-                     no_producer=args.no_producer,
+                     no_producer=args.no_producer, generic_chunk=args.generic_chunk,
                      graph=args.graph, tune=tune)
     plan.upload(stream=stream if args.graph else None)
     out = plan.alloc_outputs()
@@ -347,7 +349,7 @@ def main():
         "config": {"workload": w.name, "instances": len(qs), "m": int(qs[0].m) if len(qs) == 1 else None,
                    "n_vars": n_vars, "replicas": w.replicas, "sweeps": w.sweeps, "T0": w.T0, "T1": w.T1,
                    "seed": w.seed, "kernel": args.kernel, "persistent": args.persistent, "graph": args.graph,
-                   "no_producer": args.no_producer,
+                   "no_producer": args.no_producer, "generic_chunk": args.generic_chunk,
                    "tune": repr(tune) if tune is not None else None, "attempts_per_step": attempts,
                    "accept_rate": float(acc.sum() / attempts), "draw_rate": float(drw.sum() / attempts),
                    "best_E": [int(v) for v in out.inst_best_E.cpu().numpy()[:4]]},

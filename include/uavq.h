@@ -169,6 +169,9 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
                                       along the schedule: plan_create checks, EINVAL otherwise), so
                                       every output is the same; the launch ends when all are frozen.
                                       Not for throughput measurements: frozen sweeps are not evaluated. */
+#define UAVQ_VARIANT_GENERIC 0x400u /* 64 < m <= 192: the generic chunked walk (every step walked) instead
+                                      of the kernel that first tests blocks of four steps whose steps
+                                      each hold one cell (a schedule choice; same results) */
 #define UAVQ_REDUCE_AT_END 0x200u  /* uavq_anneal_segment fills the per-instance outputs (inst_best_*)
                                       only in a segment that ends the schedule (s_end = S); earlier
                                       segments leave them untouched.  Per-replica outputs are unchanged. */
@@ -177,7 +180,7 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
 typedef struct {
     int32_t waves_per_block[7];  /* per chunk class c = ceil(m/64) (index 0 unused); 0 = default;
                                     classes 4..6 run at most 4 per block */
-    uint32_t variant_flags;      /* 0, UAVQ_VARIANT_ROWMASK and/or UAVQ_VARIANT_NOPRODUCER */
+    uint32_t variant_flags;      /* 0 or UAVQ_VARIANT_ROWMASK / _NOPRODUCER / _GENERIC */
     float trial_ms;              /* measured time of the chosen shape (trial run) */
 } uavq_tune;
 

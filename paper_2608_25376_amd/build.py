@@ -7,7 +7,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuavq.so")
-SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_refresh.hip", "uavq_warm.hip", "uavq_pt.hip"]
+SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_sweep_chunk.hip", "uavq_refresh.hip", "uavq_warm.hip",
+           "uavq_pt.hip"]
 HEADERS = ["uavq_internal.h", "uavq_device.h", os.path.join("..", "..", "include", "uavq.h")]
 ARCH = os.environ.get("UAVQ_OFFLOAD_ARCH", "gfx950")
 
@@ -44,7 +45,8 @@ def build(force: bool = True, verbose: bool = False) -> str:
     # The chunked walk's per-chunk loops must unroll fully for five and six
     # chunks (m <= 384), or the lane's arrays move to scratch memory; the other
     # kernels of the file compile to the same code with or without this.
-    per_file = {"uavq_kernels.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+    per_file = {"uavq_kernels.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
+                "uavq_sweep_chunk.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
     objs, cmds = [], []
     for s in SOURCES:
         src = os.path.join(CSRC, s)

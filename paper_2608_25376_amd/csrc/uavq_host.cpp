@@ -407,6 +407,8 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     if (p->tune) pl->variant = p->tune->variant_flags & UAVQ_VARIANT_ROWMASK;
     pl->no_producer = (p->flags & UAVQ_VARIANT_NOPRODUCER) ? 1 : 0;
     if (p->tune) pl->no_producer = (p->tune->variant_flags & UAVQ_VARIANT_NOPRODUCER) ? 1 : 0;
+    pl->generic_chunk = (p->flags & UAVQ_VARIANT_GENERIC) ? 1 : 0;
+    if (p->tune) pl->generic_chunk = (p->tune->variant_flags & UAVQ_VARIANT_GENERIC) ? 1 : 0;
     pl->stop_frozen = (p->flags & UAVQ_STOP_FROZEN) ? 1 : 0;
     pl->reduce_at_end = (p->flags & UAVQ_REDUCE_AT_END) ? 1 : 0;
     pl->persistent = (p->flags & UAVQ_PERSISTENT) ? 1 : 0;

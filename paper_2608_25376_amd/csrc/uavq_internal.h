@@ -124,6 +124,7 @@ struct uavq_plan {
     int32_t ylds_w1 = 0;         // the m <= 64 sweep runs at one wave per SIMD (launch fits the chip)
     int32_t ylds_pc = 0;         // ... with a cut-producing wave beside each replica's wave
     int32_t no_producer = 0;     // UAVQ_VARIANT_NOPRODUCER
+    int32_t generic_chunk = 0;   // UAVQ_VARIANT_GENERIC
     int32_t stop_frozen = 0;     // UAVQ_STOP_FROZEN
     int32_t reduce_at_end = 0;   // UAVQ_REDUCE_AT_END
     size_t queue_off = 0;                 // workspace: item counters (persistent mode)
@@ -135,6 +136,8 @@ extern "C" void plan_destroy_events(uavq_plan *pl);   // also releases a cached 
 
 // Kernel launchers (uavq_kernels.hip).
 namespace uavq {
+// the block-tested chunked sweep for nj = 2, 3 chunks (uavq_sweep_chunk.hip); NULL otherwise
+const void *chunk_sweep_kernel(int nj, bool stop);
 int launch_anneal(const uavq_plan *plan, const KArgs &a, void *stream, int64_t *check_E);
 int launch_dense(const uavq_plan *plan, const KArgs &a, hipStream_t_opaque st);
 int launch_energy_refresh(const uint32_t *d_states, int64_t n, int64_t *d_E, const uint8_t *d_D, const uint8_t *d_dep,

@@ -97,64 +97,6 @@ __global__ __launch_bounds__(256) void k_init_states(KArgs a) {
 }
 
 // --------------------------------------------------------- factored sweep --
-// Acceptance cuts of four sites: for each, the least d >= 1 whose table entry thr(d) is
-// <= u, so that a flip with energy change dE is accepted exactly when dE < cut
-// (dE <= 0 always; 0 < dE < dcut iff u < thr(dE); thr(d) = 0 from dcut on).
-// The continuous threshold 2^32 exp(-d/T) drops to u at d = T ln 2 (32 -
-// log2 u); a guess half a step below that (e0 = 32 T ln 2 - 1/2) is the cut or
-// one short of it, which the entries d-1, d, d+1 settle.  Otherwise (never
-// seen: the guess is good to far better than half a step; or u = 2^32 - 1)
-// the table is walked.  The result depends on the table alone.  The LDS row
-// must hold valid entries up to index dcut + 1.
-__device__ __forceinline__ void accept_cuts(const uint4 &u4, float tl2, float e0, float dm1, int dcut,
-                                            const uint32_t *thr, int &cut0, int &cut1, int &cut2, int &cut3) {
-    const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
-    int d[4], cut[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const float e = fmaf(-tl2, __builtin_amdgcn_logf((float)u[i]), e0);   // u = 0: +inf
-        d[i] = (int)__builtin_amdgcn_fmed3f(e, 0.0f, dm1) + 1;                // 1..dcut
-    }
-    // all twelve entries are read unconditionally, so the reads issue together
-    uint32_t tm[4], t0[4], t1[4];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        tm[i] = thr[d[i] - 1];
-        t0[i] = thr[d[i]];
-        t1[i] = thr[d[i] + 1];
-    }
-    bool ok = true;
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        cut[i] = d[i] + (t0[i] > u[i] ? 1 : 0);
-        ok = ok & (tm[i] > u[i]) & (t1[i] <= u[i]);
-    }
-    if (ballot64(!ok)) {
-#pragma unroll
-        for (int i = 0; i < 4; i++) {
-            int c = cut[i];
-            while (c < dcut && thr[c] > u[i]) c++;
-            while (c > 1 && thr[c - 1] <= u[i]) c--;
-            cut[i] = c;
-        }
-    }
-    cut0 = cut[0];
-    cut1 = cut[1];
-    cut2 = cut[2];
-    cut3 = cut[3];
-}
-
-// Philox words of one lane's block of four steps and their exact cuts, packed
-// as four uint16 (the m <= 64 producer/consumer sweep's fallback when no
-// producer made them; out of line, as it is rarely taken).
-__device__ __attribute__((noinline)) uint2 draw_cuts(uint32_t cbase, uint32_t s, uint32_t r, uint32_t inst, uint32_t seed,
-                                                     float tl2, float e0, float dm1, int dcut, const uint32_t *thr) {
-    const uint4 u4 = philox(make_uint4(cbase, s, r, inst), seed, 0u);
-    int c0, c1, c2, c3;
-    accept_cuts(u4, tl2, e0, dm1, dcut, thr, c0, c1, c2, c3);
-    return make_uint2((uint32_t)c0 | ((uint32_t)c1 << 16), (uint32_t)c2 | ((uint32_t)c3 << 16));
-}
-
 template <int NJ>
 struct RowOps {
     // mask of the step held by lane lt of one chunk of the step masks
@@ -589,18 +531,6 @@ __device__ __forceinline__ void factored_item(const KArgs &a, int itx, uint8_t *
             a.draws[grep] = ndraw;
         }
     }
-}
-
-// Work-item loop: one item per block, or (persistent mode) items pulled in
-// order from a counter until the class is exhausted.
-__device__ __forceinline__ int next_item(const KArgs &a, int iter) {
-    __shared__ int s_item;
-    if (!a.queue) return iter == 0 ? a.item_base + (int)blockIdx.x : -1;
-    __syncthreads();
-    if (threadIdx.x == 0) s_item = atomicAdd(a.queue, 1);
-    __syncthreads();
-    const int k = s_item;
-    return k < a.queue_n ? a.item_base + k : -1;
 }
 
 template <int NJ, bool STOP>
@@ -1235,6 +1165,7 @@ static const void *class_kernel_t(const uavq_plan *pl, int cls) {
     if (cls == 1 && use_ylds(pl))
         return pl->ylds_w1 ? (const void *)k_sweep_ylds_w1<STOP> : (const void *)k_sweep_ylds<STOP>;
     if (cls == 1) return (const void *)k_sweep_factored<1, STOP>;
+    if ((cls == 2 || cls == 3) && !pl->generic_chunk) return chunk_sweep_kernel(cls, STOP);
     if (cls == 2) return (const void *)k_sweep_factored<2, STOP>;
     if (cls == 3) return (const void *)k_sweep_factored<3, STOP>;
     if (cls == 4) return (const void *)k_sweep_factored4<STOP>;
@@ -1403,6 +1334,8 @@ const char *uavq_plan_kernel_name(const uavq_plan *pl, int32_t cls) {
     if (uavq::prepare(pl)) return nullptr;   // the one-wave choice needs the device's CU count
     if (cls == 1 && uavq::use_ylds(pl) && pl->ylds_pc) return "k_sweep_ylds_pc";
     if (cls == 1 && uavq::use_ylds(pl)) return pl->ylds_w1 ? "k_sweep_ylds_w1" : "k_sweep_ylds";
+    if (cls == 2 && !pl->generic_chunk) return "k_sweep_chunk<2>";
+    if (cls == 3 && !pl->generic_chunk) return "k_sweep_chunk<3>";
     static const char *const names[] = {"", "k_sweep_factored<1>", "k_sweep_factored<2>", "k_sweep_factored<3>",
                                         "k_sweep_factored4", "k_sweep_factored_wide<5>", "k_sweep_factored_wide<6>"};
     static_assert(sizeof(names) / sizeof(names[0]) == uavq::kMaxChunks + 1, "one name per chunk class");

@@ -23,6 +23,7 @@ VARIANT_ROWMASK = 0x10
 PERSISTENT = 0x20
 GRAPH = 0x40
 VARIANT_NOPRODUCER = 0x80
+VARIANT_GENERIC = 0x400
 STOP_FROZEN = 0x100
 REDUCE_AT_END = 0x200
 CHUNK_CLASSES = 6          # sweep kernel classes by ceil(m / 64); m <= 384
@@ -328,7 +329,8 @@ class Plan:
     def __init__(self, qubos: Sequence[Qubo], inst_ids: Sequence[int], replicas: int, sweeps: int, T0: float,
                  T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
                  rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None,
-                 no_producer: bool = False, stop_frozen: bool = False, inst_T=None, reduce_at_end: bool = False):
+                 no_producer: bool = False, stop_frozen: bool = False, inst_T=None, reduce_at_end: bool = False,
+                 generic_chunk: bool = False):
         """``inst_T``: optional per-instance schedules, a sequence of (T0_i, T1_i)."""
         self.qubos = list(qubos)
         n = len(self.qubos)
@@ -338,6 +340,7 @@ class Plan:
         flags = (KERNEL_DENSE if dense else 0) | (VARIANT_ROWMASK if rowmask else 0)
         flags |= (PERSISTENT if persistent else 0) | (GRAPH if graph else 0)
         flags |= VARIANT_NOPRODUCER if no_producer else 0
+        flags |= VARIANT_GENERIC if generic_chunk else 0
         flags |= STOP_FROZEN if stop_frozen else 0
         flags |= REDUCE_AT_END if reduce_at_end else 0
         self._tune = tune

@@ -324,3 +324,35 @@ def test_largest_penalty(U, oracle_lib, rows, cols, dens, inst, R):
     assert o.P == P
     with pytest.raises(U.UavqError):
         U.qubo_build(rows, cols, nofly=g.nofly, penalty=P + 1)
+
+
+@pytest.mark.parametrize("side,dens,inst", [(9, 0.1, 80), (10, 0.0, 81), (12, 0.0, 82), (13, 0.1, 83), (14, 0.05, 84)])
+def test_block_tested_kernel_equals_generic(U, side, dens, inst):
+    """64 < m <= 192: the kernel that first tests blocks of four one-cell steps
+    gives the generic chunked walk's bytes in every output, over a whole
+    schedule (hot, middle and frozen sweeps), with seeded tours and late
+    starts among the replicas."""
+    g = inputs.grid(side, side, dens, seed=9, inst=inst)
+    m = g.n_free
+    assert 64 < m <= 192
+    R, S = 48, 400
+    rng = np.random.default_rng(inst)
+    x0 = np.zeros((R, m * m), np.uint8)
+    for r in range(R):
+        X = np.zeros((m, m), np.uint8)
+        X[np.arange(m), rng.permutation(m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = (np.arange(R) % 4 == 1).astype(np.uint8)
+    start = np.where(seeded == 1, rng.integers(0, S, size=R), 0).astype(np.int32)
+    say(f"case: block-tested vs generic {side}x{side} m={m} R={R} S={S}")
+    qa, pa, ra = gpu_anneal(U, [g], R, S, 200.0, 0.5, 6, init_x=[x0], seeded=seeded, start_sweep=start,
+                            check_E=True)
+    assert pa.kernel_name((m + 63) // 64) == f"k_sweep_chunk<{(m + 63) // 64}>"
+    qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly)]
+    plan = U.Plan(qs, [g.inst_id], R, S, 200.0, 0.5, 6, generic_chunk=True)
+    assert plan.kernel_name((m + 63) // 64) == f"k_sweep_factored<{(m + 63) // 64}>"
+    _, _, rb = gpu_anneal(U, [g], R, S, 200.0, 0.5, 6, init_x=[x0], seeded=seeded, start_sweep=start,
+                          check_E=True, generic_chunk=True)
+    for k in ra:
+        assert np.array_equal(ra[k], rb[k]), k
+    assert np.array_equal(ra["check_E"], ra["final_E"])
