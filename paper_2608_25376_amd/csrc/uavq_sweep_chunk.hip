@@ -25,10 +25,10 @@
 //    used directly as the per-lane select condition of dE and of the +-2P
 //    slope (inverse ballot), so no bit is extracted per lane.
 //
-// Per lane and chunk: K_j = 2P (C_c - 1) for valid cells and a large
-// constant for c >= m, so that padding lanes never fall below any cut.
-// 24-bit products are exact here: |k|, |na - nr| <= m, the slope is +-2P
-// with 2P < 2^21, and a cost-row entry is at most 255.
+// Per lane and chunk: KC_j = 2P C_c for valid cells and a large constant for
+// c >= m, so that padding lanes never fall below any cut.
+// 24-bit products are exact here: |k|, |na - nr| <= m and the slope is +-2P
+// with 2P < 2^21.
 #include <hip/hip_runtime.h>
 
 #include <climits>
@@ -42,25 +42,30 @@ namespace {
 
 constexpr int kBigK = 1 << 29;   // K of padding lanes: dE stays far above every cut
 
+// LDS pointers with their address space spelled out, so that offsets stay
+// 32-bit (a generic pointer makes the compiler form 64-bit addresses)
+typedef __attribute__((address_space(3))) uint8_t lds_u8;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
 __device__ __forceinline__ bool lane_in_mask(uint32_t lo, uint32_t hi) {
     return __builtin_amdgcn_inverse_ballot_w64(((uint64_t)hi << 32) | (uint64_t)lo);
 }
 
 __device__ __forceinline__ uint32_t rl(uint32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
-__device__ __forceinline__ int rli(int v, int lane) { return (int)__builtin_amdgcn_readlane((uint32_t)v, lane); }
 // value v into the lane `lane` of old (one compare shared by the caller's selects)
 __device__ __forceinline__ uint32_t wl(uint32_t v, bool mine, uint32_t old) { return mine ? v : old; }
 
-// step summary R | (p << 16): R set cells, p the lowest set cell (0 if none)
+// step summary R | (p m << 16): R set cells, p the lowest set cell (0 if
+// none), kept as the offset p m of its cost row (< 2^16 for m <= 192)
 template <int NJ>
-__device__ __forceinline__ int summary(const uint32_t (&mk)[2 * NJ]) {
-    int R = 0, p = 0;
+__device__ __forceinline__ uint32_t summary(const uint32_t (&mk)[2 * NJ], int m) {
+    uint32_t R = 0, p = 0;
 #pragma unroll
     for (int w = 2 * NJ - 1; w >= 0; w--) {
-        R += __popc(mk[w]);
-        if (mk[w]) p = 32 * w + __builtin_ctz(mk[w]);
+        R += (uint32_t)__popc(mk[w]);
+        if (mk[w]) p = 32u * (uint32_t)w + (uint32_t)__builtin_ctz(mk[w]);
     }
-    return R | (p << 16);
+    return R | ((p * (uint32_t)m) << 16);   // unsigned: p m may reach bit 31 after the shift
 }
 
 }  // namespace
@@ -79,9 +84,10 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
     const int srow = d.sched_row, dstep = d.sched_step;
 
     // LDS: the acceptance-table row | D (m*m bytes) | start-cell costs (m bytes)
-    uint32_t *sthr = reinterpret_cast<uint32_t *>(smem);
-    uint8_t *sD = smem + 4 * (size_t)Ts;
-    uint8_t *sdep = sD + al16((size_t)m * m);
+    lds_u8 *const lsm = (lds_u8 *)smem;
+    lds_u32 *const sthr = (lds_u32 *)lsm;
+    lds_u8 *const sD = lsm + 4 * Ts;
+    lds_u8 *const sdep = sD + (int)al16((size_t)m * m);
     __shared__ int s_first_sh;
     __shared__ int s_live[2];
 
@@ -89,8 +95,10 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
         const uint4 *gD = reinterpret_cast<const uint4 *>(a.ws + d.d_off);
         const uint4 *gdep = reinterpret_cast<const uint4 *>(a.ws + d.ddep_off);
         const int nD4 = (m * m + 15) >> 4, nd4 = (m + 15) >> 4;
-        for (int i = threadIdx.x; i < nD4; i += nthr) reinterpret_cast<uint4 *>(sD)[i] = gD[i];
-        for (int i = threadIdx.x; i < nd4; i += nthr) reinterpret_cast<uint4 *>(sdep)[i] = gdep[i];
+        uint4 *gsD = reinterpret_cast<uint4 *>(smem + 4 * (size_t)Ts);   // the copies go through generic pointers
+        uint4 *gsdep = reinterpret_cast<uint4 *>(smem + 4 * (size_t)Ts + al16((size_t)m * m));
+        for (int i = threadIdx.x; i < nD4; i += nthr) gsD[i] = gD[i];
+        for (int i = threadIdx.x; i < nd4; i += nthr) gsdep[i] = gdep[i];
     }
 
     const bool active = wave < it.nrep;
@@ -108,7 +116,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
     if (s_first < a.s_end) {
         const int n4 = (a.dcut[srow + s_first * dstep] + 2 + 3) >> 2;   // through index dcut + 1
         const uint4 *src = reinterpret_cast<const uint4 *>(a.thr + (size_t)(srow + s_first * dstep) * Ts);
-        uint4 *dst = reinterpret_cast<uint4 *>(sthr);
+        uint4 *dst = reinterpret_cast<uint4 *>(smem);
         for (int i = threadIdx.x; i < n4; i += nthr) dst[i] = src[i];
     }
     __syncthreads();
@@ -176,7 +184,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     while (bits) {
                         const int b = __builtin_ctz(bits);
                         bits &= bits - 1u;
-                        const uint8_t *row = sD + (32 * w + b) * m;
+                        const lds_u8 *row = sD + __umul24(32 * w + b, m);   // 24-bit product: one full-rate multiply-add
 #pragma unroll
                         for (int j = 0; j < NJ; j++) Yt[j] += row[64 * j + L];
                     }
@@ -189,12 +197,14 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
             if (64 * j + L < m) lane_e += (int64_t)d.P * Cc[j] * (Cc[j] - 1);
         E = d.c0 + rowterm + wave_sum64(lane_e);
     }
-    int K[NJ];     // 2P (C_c - 1); padding lanes far above every cut
-    int si[NJ];    // step summaries of steps 64 j + L + 1
+    int KC[NJ];    // 2P C_c; padding lanes far above every cut
+    uint32_t si[NJ];    // step summaries of steps 64 j + L + 1
+    uint32_t ckey[NJ];  // the summary of a step that holds exactly this lane's cell
 #pragma unroll
     for (int j = 0; j < NJ; j++) {
-        K[j] = 64 * j + L < m ? twoP * (Cc[j] - 1) : kBigK;
-        si[j] = summary<NJ>(rm[j]);
+        KC[j] = 64 * j + L < m ? twoP * Cc[j] : kBigK;
+        si[j] = summary<NJ>(rm[j], m);
+        ckey[j] = (((uint32_t)(64 * j + L) * (uint32_t)m) << 16) | 1u;
     }
 
     int64_t bestE = LLONG_MAX;
@@ -205,22 +215,21 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
         bestS = a.best_sweep[grep];
     }
     int64_t Elane = 0;         // energy change of the lane's accepted flips in the current sweep
-    uint32_t ndraw_lane = 0;   // draws counted per lane (walked steps)
     bool frozen = false;
 
     // travel row of step t (uniform) for this lane's cells: the start-cell costs
     // at t = m + 1 (closed tour), 0 past it; from the summary when the step holds
     // one cell, from its mask otherwise.  q = the step's lane in chunk jq.
-    auto yrow = [&](int t, int sv, const uint32_t *mkq, int (&Y)[NJ]) {
+    auto yrow = [&](int t, uint32_t sv, const uint32_t *mkq, int (&Y)[NJ]) {
         if (t > m) {
 #pragma unroll
             for (int j = 0; j < NJ; j++) Y[j] = (t == m + 1 && d.closed) ? dep[j] : 0;
             return;
         }
-        const int R = sv & 0xffff;
+        const uint32_t R = sv & 0xffffu;
         if (R == 1) {
             // lanes past m read bytes beyond the row (inside the LDS allocation); unused
-            const uint8_t *row = sD + (sv >> 16) * m;
+            const lds_u8 *row = sD + (sv >> 16);
 #pragma unroll
             for (int j = 0; j < NJ; j++) Y[j] = row[64 * j + L];
             return;
@@ -234,7 +243,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
             while (bits) {
                 const int b = __builtin_ctz(bits);
                 bits &= bits - 1u;
-                const uint8_t *row = sD + (32 * w + b) * m;
+                const lds_u8 *row = sD + __umul24(32 * w + b, m);   // 24-bit product: one full-rate multiply-add
 #pragma unroll
                 for (int j = 0; j < NJ; j++) Y[j] += row[64 * j + L];
             }
@@ -252,13 +261,12 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
             const int i = threadIdx.x + k * nthr;
             pre[k] = has_next ? src_next[i < n4_next ? i : 0] : make_uint4(0u, 0u, 0u, 0u);
         }
-        const uint32_t *thr = sthr;
+        const lds_u32 *thr = sthr;
         const int dcut = uniform_load(a.dcut, srow + s * dstep);
         const float tl2 = __builtin_amdgcn_exp2f(d.tl2_a + d.tl2_b * (float)s);   // ~ T_s ln 2
         const float e0 = 32.0f * tl2 - 0.5f, dm1 = (float)(dcut - 1);
         if (STOP && threadIdx.x == 0) s_live[(s + 1) & 1] = 0;
         if (active && s >= s0 && !frozen) {
-            const uint32_t ndl0 = ndraw_lane;
             uint32_t nacc_s = 0, ndraw_s = 0;
             // window of travel rows Y_{t0-1} .. Y_{t0+4} of the current block
             int Yw[6][NJ];
@@ -267,7 +275,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
 #pragma unroll
             for (int k = 1; k <= 5; k++) {
                 uint32_t mk[2 * NJ];
-                const int sv = rli(si[0], k - 1);
+                const uint32_t sv = rl(si[0], k - 1);
                 if ((sv & 0xffff) > 1)
 #pragma unroll
                     for (int w = 0; w < 2 * NJ; w++) mk[w] = rl(rm[0][w], k - 1);
@@ -280,18 +288,20 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     const int t0 = 64 * jt + q0 + 1;
                     if (t0 > m) break;
                     const int tb = (t0 - 1) >> 2;
-                    int sx[4];   // summaries of the block's steps
+                    uint32_t sx[4];   // summaries of the block's steps
 #pragma unroll
-                    for (int i = 0; i < 4; i++) sx[i] = rli(si[jt], q0 + i);
+                    for (int i = 0; i < 4; i++) sx[i] = rl(si[jt], q0 + i);
 
-                    // ---- quiet-block test (every step of the block holds one cell)
+                    // ---- quiet-block test (every step of the block holds one cell: the
+                    // low halves of the four summaries are all 1)
                     bool done = false;
-                    const bool tours = spec && t0 + 3 <= m && (sx[0] & 0xffff) == 1 && (sx[1] & 0xffff) == 1 &&
-                                       (sx[2] & 0xffff) == 1 && (sx[3] & 0xffff) == 1;
-                    // R_t = 1: dE = A + 2P for x = 0 and 2P - A for x = 1, A = Y_{t-1} + Y_{t+1} + K
+                    const uint32_t s_or = sx[0] | sx[1] | sx[2] | sx[3], s_and = sx[0] & sx[1] & sx[2] & sx[3];
+                    const bool tours = spec && t0 + 3 <= m && (s_or & 0xfffe) == 0 && (s_and & 1);
+                    // R_t = 1: dE = v for x = 0 and 4P - v for x = 1, v = Y_{t-1} + Y_{t+1} + 2P C_c;
+                    // x = 1 exactly at the lane whose cell the summary names
                     auto dEq = [&](int i, int j) {
-                        const int v = Yw[i][j] + Yw[i + 2][j] + K[j] + twoP;
-                        return (64 * j + L == (sx[i] >> 16)) ? fourP - v : v;
+                        const int v = Yw[i][j] + Yw[i + 2][j] + KC[j];
+                        return ckey[j] == sx[i] ? fourP - v : v;
                     };
                     if (tours) {
                         int mn = INT_MAX;
@@ -350,13 +360,13 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             uint32_t mc[2 * NJ];
 #pragma unroll
                             for (int w = 0; w < 2 * NJ; w++) mc[w] = rl(rm[jt][w], lt);
-                            const int hR0 = twoP * (sx[i] & 0xffff);
+                            const int hR1 = twoP * ((int)(sx[i] & 0xffffu) - 1);   // 2P (R_t - 1)
                             int dE0[NJ], dpl[NJ];
                             bool xb[NJ];
 #pragma unroll
                             for (int j = 0; j < NJ; j++) {
                                 xb[j] = lane_in_mask(mc[2 * j], mc[2 * j + 1]);
-                                const int v = Yw[i][j] + Yw[i + 2][j] + K[j] + hR0;
+                                const int v = Yw[i][j] + Yw[i + 2][j] + KC[j] + hR1;
                                 dE0[j] = xb[j] ? fourP - v : v;
                                 dpl[j] = xb[j] ? -twoP : twoP;   // change of dE per net 1 gained by step t
                             }
@@ -366,7 +376,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             // a step with no site below the cut is finished: no accept, no draw
                             if (!ballot64(mnv < dcut)) continue;
                             const int ti = i;
-                            int k = 0, psg = 0;
+                            int k = 0, psn = 0;   // psn: 0 while the pending cost row adds, -1 when it subtracts
                             uint64_t accd[NJ];
                             int dY[NJ], pd[NJ];
 #pragma unroll
@@ -376,20 +386,20 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                 pd[j] = 0;
                             }
                             // flip the first accepted site of chunk j's mask am; its cost-row
-                            // entries are read now and added at the next flip
+                            // entries are read now and added (or subtracted) at the next flip
                             auto flip = [&](int j, uint64_t am, uint64_t &openm) {
                                 const int Ls = __builtin_ctzll(am);
                                 accd[j] |= 1ull << Ls;
                                 const uint64_t rowj = ((uint64_t)mc[2 * j + 1] << 32) | (uint64_t)mc[2 * j];
                                 const bool clears = (rowj >> Ls) & 1ull;
 #pragma unroll
-                                for (int jj = 0; jj < NJ; jj++) dY[jj] += __mul24(psg, pd[jj]);
-                                const uint8_t *drow = sD + (64 * j + Ls) * m;
+                                for (int jj = 0; jj < NJ; jj++) dY[jj] += (pd[jj] ^ psn) - psn;
+                                const lds_u8 *drow = sD + (64 * j + Ls) * m;
 #pragma unroll
                                 for (int jj = 0; jj < NJ; jj++) pd[jj] = drow[64 * jj + L];
-                                psg = clears ? -1 : 1;
-                                k += psg;
-                                openm &= ~1ull << Ls;
+                                psn = clears ? -1 : 0;
+                                k += clears ? -1 : 1;
+                                openm &= ~1ull << Ls;   // the walk resumes after Ls
                             };
 #pragma unroll
                             for (int j = 0; j < NJ; j++) {
@@ -405,7 +415,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                             have_cut |= 1u << j;
                                             const uint2 cw = draw_cuts((uint32_t)(64 * j + L) + 65536u * (uint32_t)tb,
                                                                        (uint32_t)s, (uint32_t)r, d.inst_id, a.seed, tl2,
-                                                                       e0, dm1, dcut, thr);
+                                                                       e0, dm1, dcut, (const uint32_t *)thr);
                                             cutp[j][0] = cw.x;
                                             cutp[j][1] = cw.y;
                                             break;
@@ -439,7 +449,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                         ballot64((uint32_t)(dE0[j] - 1) < (uint32_t)(dcut - 1)));
                             } else {
 #pragma unroll
-                                for (int jj = 0; jj < NJ; jj++) dY[jj] += __mul24(psg, pd[jj]);
+                                for (int jj = 0; jj < NJ; jj++) dY[jj] += (pd[jj] ^ psn) - psn;
                                 // visit-time dE of every site (dE0 plus the slope per net flip
                                 // before it in site order), then draws, energy, counts and masks
                                 int nab = 0, nrb = 0;   // adds / removes in earlier chunks
@@ -454,10 +464,10 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                                              (uint32_t)(rems >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)rems, 0u));
                                     const int dEv = dE0[j] + __mul24(na - nr, dpl[j]);
-                                    ndraw_lane += (uint32_t)(dEv - 1) < (uint32_t)(dcut - 1) ? 1u : 0u;
-                                    const bool inA = (accd[j] >> L) & 1ull;
+                                    ndraw_s += (uint32_t)__popcll(ballot64((uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)));
+                                    const bool inA = lane_in_mask((uint32_t)accd[j], (uint32_t)(accd[j] >> 32));
                                     Elane += inA ? dEv : 0;
-                                    K[j] += inA ? dpl[j] : 0;
+                                    KC[j] += inA ? dpl[j] : 0;
                                     Yw[i + 1][j] += dY[j];
                                     nab += (int)__popcll(adds);
                                     nrb += (int)__popcll(rems);
@@ -471,7 +481,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                 const bool mine = L == lt;
 #pragma unroll
                                 for (int w = 0; w < 2 * NJ; w++) rm[jt][w] = wl(mc[w], mine, rm[jt][w]);
-                                si[jt] = (int)wl((uint32_t)summary<NJ>(mc), mine, (uint32_t)si[jt]);
+                                si[jt] = wl(summary<NJ>(mc, m), mine, si[jt]);
                             }
                         }
                         spec = nacc_s == acc_before;
@@ -484,31 +494,51 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                         Yw[0][j] = Yw[4][j];
                         Yw[1][j] = Yw[5][j];
                     }
+                    {
+                        uint32_t sv[4];
+                        if (q0 <= 52 || jt + 1 >= NJ) {
 #pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        const int q = q0 + 5 + k, t = t0 + 5 + k;
-                        int sv = 0;
-                        uint32_t mk[2 * NJ];
-                        if (t <= m) {
-                            if (q < 64 || jt + 1 >= NJ) {
-                                sv = rli(si[jt], q & 63);
-                                if ((sv & 0xffff) > 1)
+                            for (int k = 0; k < 4; k++) sv[k] = rl(si[jt], min(q0 + 5 + k, 63));   // past 63: t > m
+                        } else {
 #pragma unroll
-                                    for (int w = 0; w < 2 * NJ; w++) mk[w] = rl(rm[jt][w], q & 63);
-                            } else {
-                                sv = rli(si[jt + 1 < NJ ? jt + 1 : jt], q - 64);
-                                if ((sv & 0xffff) > 1)
-#pragma unroll
-                                    for (int w = 0; w < 2 * NJ; w++) mk[w] = rl(rm[jt + 1 < NJ ? jt + 1 : jt][w], q - 64);
+                            for (int k = 0; k < 4; k++) {
+                                const int q = q0 + 5 + k;
+                                sv[k] = q < 64 ? rl(si[jt], q) : rl(si[jt + 1 < NJ ? jt + 1 : jt], q - 64);
                             }
                         }
-                        yrow(t, sv, mk, Yw[2 + k]);
+                        const uint32_t l_or = sv[0] | sv[1] | sv[2] | sv[3], l_and = sv[0] & sv[1] & sv[2] & sv[3];
+                        if (t0 + 8 <= m && (l_or & 0xfffe) == 0 && (l_and & 1)) {
+                            // four one-cell steps: their cost rows
+#pragma unroll
+                            for (int k = 0; k < 4; k++) {
+                                const lds_u8 *row = sD + (sv[k] >> 16);
+#pragma unroll
+                                for (int j = 0; j < NJ; j++) Yw[2 + k][j] = row[64 * j + L];
+                            }
+                        } else {
+#pragma unroll
+                            for (int k = 0; k < 4; k++) {
+                                const int q = q0 + 5 + k, t = t0 + 5 + k;
+                                uint32_t mk[2 * NJ];
+                                if (t <= m && (sv[k] & 0xffff) > 1) {
+                                    if (q < 64 || jt + 1 >= NJ) {
+#pragma unroll
+                                        for (int w = 0; w < 2 * NJ; w++) mk[w] = rl(rm[jt][w], q & 63);
+                                    } else {
+#pragma unroll
+                                        for (int w = 0; w < 2 * NJ; w++)
+                                            mk[w] = rl(rm[jt + 1 < NJ ? jt + 1 : jt][w], q - 64);
+                                    }
+                                }
+                                yrow(t, sv[k], mk, Yw[2 + k]);
+                            }
+                        }
                     }
                 }
             }
             nacc += nacc_s;
             ndraw += ndraw_s;
-            if (STOP && nacc_s == 0 && ndraw_s == 0 && !ballot64(ndraw_lane != ndl0)) frozen = true;
+            if (STOP && nacc_s == 0 && ndraw_s == 0) frozen = true;
             if (nacc_s) {
                 E += wave_sum64(Elane);
                 Elane = 0;
@@ -532,7 +562,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
         __syncthreads();
         const bool all_frozen = STOP && s_live[s & 1] == 0;
         if (has_next) {
-            uint4 *dst = reinterpret_cast<uint4 *>(sthr);
+            uint4 *dst = reinterpret_cast<uint4 *>(smem);
 #pragma unroll
             for (int k = 0; k < KP; k++) {
                 const int i = threadIdx.x + k * nthr;
@@ -553,7 +583,6 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                 for (int w = 0; w < 2 * NJ; w++)
                     if (w < W) st[(t - 1) * W + w] = rm[j][w];
         }
-        ndraw += (uint64_t)wave_sum64((int64_t)ndraw_lane);
         if (L == 0) {
             if (a.resume) {
                 nacc += a.accepts[grep];

@@ -28,10 +28,12 @@ def U():
     ("pc", [(8, 8, 0.1, 0)], 96, 400, {}, 1, "k_sweep_ylds_pc"),
     ("w1", [(7, 7, 0.0, 1)], 64, 400, {"no_producer": True}, 1, "k_sweep_ylds_w1"),
     ("ylds", [(6, 6, 0.1, 2)], 64, 300, {"wpb": 8}, 1, "k_sweep_ylds"),
-    ("factored2", [(9, 9, 0.1, 3)], 32, 300, {}, 2, "k_sweep_factored<2>"),
-    ("factored3", [(12, 12, 0.0, 4)], 16, 200, {}, 3, "k_sweep_factored<3>"),
+    ("chunk2", [(9, 9, 0.1, 3)], 32, 300, {}, 2, "k_sweep_chunk<2>"),
+    ("chunk3", [(12, 12, 0.0, 4)], 16, 200, {}, 3, "k_sweep_chunk<3>"),
+    ("factored2", [(9, 9, 0.1, 3)], 32, 300, {"generic_chunk": True}, 2, "k_sweep_factored<2>"),
+    ("factored3", [(12, 12, 0.0, 4)], 16, 200, {"generic_chunk": True}, 3, "k_sweep_factored<3>"),
     ("persistent_batch", [(4, 4, 0.0, 5), (10, 10, 0.1, 6), (5, 6, 0.2, 7)], 24, 300, {"persistent": True}, 2,
-     "k_sweep_factored<2>"),
+     "k_sweep_chunk<2>"),
 ])
 def test_stop_frozen_identical(U, case, grids, R, S, kw, cls, kernel):
     gs = [inputs.grid(r, c, d, seed=3, inst=i) for r, c, d, i in grids]
