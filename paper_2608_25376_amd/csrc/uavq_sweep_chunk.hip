@@ -282,6 +282,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                 yrow(k, sv, mk, Yw[k]);
             }
             bool spec = true;
+            bool eager = false;   // the last walked block drew in every chunk (hot): draw this block's up front
 #pragma unroll
             for (int jt = 0; jt < NJ; jt++) {
                 for (int q0 = 0; q0 < 64; q0 += 4) {
@@ -352,6 +353,23 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                         const uint32_t acc_before = nacc_s;
                         uint32_t have_cut = 0;   // bit j: chunk j's cuts of this block are known
                         uint32_t cutp[NJ][2];
+                        if (eager) {
+                            // every chunk is likely to need its words: draw them all here, in one
+                            // branch-free stretch (the cuts depend on the words and the table only)
+#pragma unroll
+                            for (int j = 0; j < NJ; j++) {
+                                const uint4 u4 = philox(
+                                    make_uint4((uint32_t)(64 * j + L) + 65536u * (uint32_t)tb, (uint32_t)s, (uint32_t)r,
+                                               d.inst_id),
+                                    a.seed, 0u);
+                                int c0, c1, c2, c3;
+                                accept_cuts(u4, tl2, e0, dm1, dcut, (const uint32_t *)thr, c0, c1, c2, c3);
+                                cutp[j][0] = (uint32_t)c0 | ((uint32_t)c1 << 16);
+                                cutp[j][1] = (uint32_t)c2 | ((uint32_t)c3 << 16);
+                            }
+                            have_cut = (1u << NJ) - 1u;
+                        }
+                        uint32_t drawn = 0;   // bit j: a site of chunk j needed a draw in this block
 #pragma unroll
                         for (int i = 0; i < 4; i++) {
                             const int t = t0 + i;
@@ -444,9 +462,12 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             if (!any) {
                                 // no flip: every site was visited with its dE0
 #pragma unroll
-                                for (int j = 0; j < NJ; j++)
-                                    ndraw_s += (uint32_t)__popcll(
+                                for (int j = 0; j < NJ; j++) {
+                                    const uint32_t nd = (uint32_t)__popcll(
                                         ballot64((uint32_t)(dE0[j] - 1) < (uint32_t)(dcut - 1)));
+                                    ndraw_s += nd;
+                                    drawn |= nd ? 1u << j : 0u;
+                                }
                             } else {
 #pragma unroll
                                 for (int jj = 0; jj < NJ; jj++) dY[jj] += (pd[jj] ^ psn) - psn;
@@ -464,7 +485,10 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                                              (uint32_t)(rems >> 32),
                                                              __builtin_amdgcn_mbcnt_lo((uint32_t)rems, 0u));
                                     const int dEv = dE0[j] + __mul24(na - nr, dpl[j]);
-                                    ndraw_s += (uint32_t)__popcll(ballot64((uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)));
+                                    const uint32_t nd =
+                                        (uint32_t)__popcll(ballot64((uint32_t)(dEv - 1) < (uint32_t)(dcut - 1)));
+                                    ndraw_s += nd;
+                                    drawn |= nd ? 1u << j : 0u;
                                     const bool inA = lane_in_mask((uint32_t)accd[j], (uint32_t)(accd[j] >> 32));
                                     Elane += inA ? dEv : 0;
                                     KC[j] += inA ? dpl[j] : 0;
@@ -485,6 +509,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             }
                         }
                         spec = nacc_s == acc_before;
+                        eager = drawn == (1u << NJ) - 1u && !spec;
                     }
                     // shift the window by four steps; the new rows (steps t0+5 .. t0+8:
                     // lanes q0+5.. of chunk jt, or of chunk jt+1 past lane 63) were not

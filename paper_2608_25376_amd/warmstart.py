@@ -5,13 +5,18 @@ forward/backward/Adam, quantisation, sampling) runs in libuavq's kernels;
 this module moves tensors between those calls.
 
 Protocol (all inputs synthetic, 10x10 fields, no-fly density U[0, 0.2]):
+  0. schedule: the annealing schedule of the whole study (labels and
+     evaluation) is chosen on training instances only, among geometric
+     schedules and constant temperatures, by the mean gap of their best
+     energies at a fixed budget;
   1. label: anneal the training instances (ids from 10000) and take each
      instance's best tour, oriented so that its first visited cell has the
      smaller free-list index (a tour and its reversal cost the same);
   2. train the per-cell network to predict the visiting step of every cell;
   3. time-to-target on held-out instances (ids from 20000): the smallest
      sweep budget S of a ladder at which the best energy is within 1% of the
-     best known energy (100 E <= 101 E_best_known), for
+     best known energy (100 E <= 101 E_best_known; best known = the minimum
+     over every run made, reference runs of several schedules included), for
        plain   - one launch per instance, all replicas random,
        batched - all instances in one persistent launch,
        warm    - half of the replicas seeded with tours sampled from the
@@ -88,17 +93,43 @@ def label_data(grids, R, S, T0, T1, seed, chunk=200, log=None):
         qs = _qubos(part)
         plan, out, dt = _anneal(qs, part, R, S, T0, T1, seed)
         ms += dt
-        for (E, order), q in zip(best_tours(plan, qs, out), qs):
+        for (E, order), q, g in zip(best_tours(plan, qs, out), qs, part):
             if order is None:
                 continue
             order = canonical(order)
             labels = np.empty(q.m, np.int32)
             labels[order] = np.arange(q.m, dtype=np.int32)     # cell -> step (0-based)
-            data.append((uavq.mlp_features(q), labels, q.m))
+            data.append((uavq.mlp_features(q), labels, q.m, g))
         del plan, out
         if log:
             log(f"labelled {min(c0 + chunk, len(grids))}/{len(grids)} ({ms / 1e3:.1f} s of annealing)")
     return data, ms
+
+
+# Candidate schedules of step 0: (T0, T1); equal ends are a constant temperature.
+SCHEDULE_CANDIDATES = [(200.0, 0.5), (100.0, 1.0), (50.0, 5.0), (30.0, 10.0), (25.0, 12.0), (8.0, 8.0), (10.0, 10.0),
+                       (12.0, 12.0), (14.0, 14.0), (16.0, 16.0), (18.0, 18.0), (20.0, 20.0), (25.0, 25.0)]
+
+
+def choose_schedule(grids, R, S, seed, candidates=SCHEDULE_CANDIDATES, log=None):
+    """Step 0, on training instances only: every candidate anneals the same
+    fields at budget S; the one with the smallest mean gap to the per-field
+    best over all candidates wins.  Returns ((T0, T1), table)."""
+    qs = _qubos(grids)
+    res = {}
+    for T0, T1 in candidates:
+        _, out, ms = _anneal(qs, grids, R, S, T0, T1, seed)
+        res[(T0, T1)] = (out.inst_best_E.cpu().numpy().astype(np.float64), ms)
+    best = np.min(np.stack([v[0] for v in res.values()]), 0)
+    table = []
+    for (T0, T1), (E, ms) in res.items():
+        gap = float(np.mean(E / best - 1.0))
+        hit = float(np.mean(100 * E <= 101 * best))
+        table.append({"T0": T0, "T1": T1, "mean_gap": gap, "fraction_within_1pct": hit, "ms": ms})
+        if log:
+            log(f"schedule {T0} -> {T1}: mean gap {gap:.4f}, within 1% {hit:.2f}, {ms:.0f} ms")
+    win = min(table, key=lambda r: r["mean_gap"])
+    return (win["T0"], win["T1"]), table
 
 
 def init_params(seed):
@@ -170,13 +201,18 @@ def warm_init(net, plan, qs, frac, s0, stream=None):
     return init, (time.perf_counter() - t0) * 1e3
 
 
-def ttt(grids, net, R, ladder, T0, T1, seed, T_warm, frac=0.5, ref_sweeps=8000, single=True, log=None):
+def ttt(grids, net, R, ladder, T0, T1, seed, T_warm, frac=0.5, ref_sweeps=8000, single=True, log=None,
+        refs=()):
+    """``refs``: further reference runs (T0, T1, sweeps) whose energies enter the best known."""
     qs = _qubos(grids)
     n = len(qs)
     runs = {}            # (mode, S) -> (per-instance best E, ms)
-    # reference run (best known)
+    # reference runs (best known): this schedule at ref_sweeps, and the extra ones
     _, out, ms = _anneal(qs, grids, R, ref_sweeps, T0, T1, seed + 1000)
     best_known = out.inst_best_E.cpu().numpy().copy()
+    for (rT0, rT1, rS) in refs:
+        _, out, ms = _anneal(qs, grids, R, rS, rT0, rT1, seed + 2000)
+        best_known = np.minimum(best_known, out.inst_best_E.cpu().numpy())
     for S in ladder:
         s0 = first_sweep_below(T0, T1, S, T_warm)
         plan, out, ms = _anneal(qs, grids, R, S, T0, T1, seed)
@@ -271,23 +307,55 @@ def merge_reports(paths):
     return out
 
 
+def mean_ce(net, data, batch=64):
+    """Mean cross-entropy per cell of the network on labelled fields, and of
+    the uniform distribution over each field's steps (log m)."""
+    import torch
+    tot, rows, uni = 0.0, 0, 0.0
+    for b in range(0, len(data), batch):
+        sel = data[b:b + batch]
+        X = torch.from_numpy(np.concatenate([d[0] for d in sel])).cuda()
+        lab = torch.from_numpy(np.concatenate([d[1] for d in sel])).cuda()
+        msteps = torch.from_numpy(np.concatenate([np.full(d[2], d[2], np.int32) for d in sel])).cuda()
+        tot += float(net.loss_grad(X, msteps, lab).cpu()[0])
+        rows += X.shape[0]
+        uni += float(sum(d[2] * np.log(d[2]) for d in sel))
+    return tot / rows, uni / rows
+
+
+def save_labels(path, data):
+    """Labels for an independent fit: per labelled instance its id, side and
+    no-fly mask (which fix its features) and the step (0-based) of every free
+    cell, concatenated in instance order."""
+    np.savez(path, ids=np.asarray([d[3].inst_id for d in data], np.int64),
+             m=np.asarray([d[2] for d in data], np.int32),
+             side=np.asarray([d[3].rows for d in data], np.int32),
+             nofly=np.stack([d[3].nofly for d in data]).astype(np.uint8),
+             labels=np.concatenate([d[1] for d in data]).astype(np.int32))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--train-n", type=int, default=2000)
     ap.add_argument("--heldout-n", type=int, default=200)
+    ap.add_argument("--schedule", default="auto",
+                    help="'auto' (chosen on training instances among SCHEDULE_CANDIDATES) or T0,T1")
+    ap.add_argument("--choose-n", type=int, default=100, help="training instances that choose the schedule")
+    ap.add_argument("--choose-sweeps", type=int, default=100)
     ap.add_argument("--label-replicas", type=int, default=4096)
-    ap.add_argument("--label-sweeps", type=int, default=2000)
+    ap.add_argument("--label-sweeps", type=int, default=400)
     ap.add_argument("--replicas", type=int, default=256)
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--ladder", default="50,100,200,400,800,1600,3200")
-    ap.add_argument("--ref-sweeps", type=int, default=8000)
+    ap.add_argument("--ladder", default="10,20,50,100,200,400,800")
+    ap.add_argument("--ref-sweeps", type=int, default=3200)
     ap.add_argument("--T-warm", type=float, default=0.0, help="0 = choose on training instances")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--seeds", default="1", help="annealing seeds of the held-out evaluation (medians reported)")
     ap.add_argument("--params", default="", help="network parameters saved by an earlier run (.npy): "
-                    "skip labelling and training")
+                    "skip labelling and training (needs --schedule T0,T1)")
+    ap.add_argument("--save-labels", default="", help="write the training labels to this .npz")
     ap.add_argument("--merge", default="", help="comma-separated reports of earlier runs: combine their seeds "
                     "and write the medians to --out (no GPU work)")
     ap.add_argument("--out", default="")
@@ -303,7 +371,16 @@ def main():
     assert torch.cuda.is_available()
     t_start = time.perf_counter()
     log = lambda s: print(f"[{time.perf_counter() - t_start:7.1f} s] {s}", flush=True)
-    T0, T1, seed = 200.0, 0.5, 1
+    seed = 1
+    sched_table = None
+    if args.schedule == "auto":
+        if args.params:
+            raise SystemExit("--params needs the schedule it was trained with (--schedule T0,T1)")
+        (T0, T1), sched_table = choose_schedule(make_instances(args.choose_n, 10000), args.replicas,
+                                                args.choose_sweeps, seed + 11, log=log)
+    else:
+        T0, T1 = (float(v) for v in args.schedule.split(","))
+    log(f"schedule {T0} -> {T1}")
     if args.params:
         net = uavq.Mlp(np.load(args.params).astype(np.float32))
         data, label_ms, curve, train_s = None, None, None, None
@@ -312,14 +389,19 @@ def main():
         train_grids = make_instances(args.train_n, 10000)
         data, label_ms = label_data(train_grids, args.label_replicas, args.label_sweeps, T0, T1, seed, log=log)
         log(f"labelled {len(data)}/{len(train_grids)} training instances in {label_ms / 1e3:.1f} s")
+        if args.save_labels:
+            save_labels(args.save_labels, data)
         net, curve, train_s = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     ladder = [int(v) for v in args.ladder.split(",")]
+    constant = T0 == T1
     T_warm = args.T_warm
-    if T_warm <= 0:
+    if constant:
+        T_warm = T0            # seeded replicas start at sweep 0: a constant schedule has no colder part
+    elif T_warm <= 0:
         # choose on a slice of the training instances only
         tune = make_instances(24, 10000)
         best = None
-        for cand in (10.0, 25.0, 50.0, 100.0):
+        for cand in (0.05 * T0, 0.125 * T0, 0.25 * T0, 0.5 * T0):
             r = ttt(tune, net, args.replicas, [ladder[len(ladder) // 2]], T0, T1, seed + 7, cand,
                     ref_sweeps=args.ref_sweeps // 2, single=False)
             g = r["modes"]["batched+warm"]["mean_gap"][ladder[len(ladder) // 2]]
@@ -328,22 +410,31 @@ def main():
                 best = (g, cand)
         T_warm = best[1]
     held = make_instances(args.heldout_n, 20000)
+    # held-out labels (best tours of a long reference run) measure what the network learned
+    held_data, _ = label_data(held, args.label_replicas, args.label_sweeps, T0, T1, seed + 3000)
+    ce_held, ce_uniform = mean_ce(net, held_data)
+    log(f"held-out cross-entropy {ce_held:.4f} (uniform {ce_uniform:.4f})")
+    refs = [(200.0, 0.5, 8000), (15.4, 15.4, 3200)]
     seeds = [int(v) for v in args.seeds.split(",")]
     reps = {}
     for sd in seeds:
         log(f"held-out evaluation, seed {sd}")
         reps[sd] = ttt(held, net, args.replicas, ladder, T0, T1, sd, T_warm, ref_sweeps=args.ref_sweeps,
-                       single=not args.no_single, log=log)
+                       single=not args.no_single, log=log, refs=refs)
     rep = dict(reps[seeds[0]])
     rep["seeds"] = seeds
     rep["per_seed"] = {str(sd): per_seed_fields(r) for sd, r in reps.items()}
     rep["median"] = seed_medians(rep["per_seed"])
+    rep.update({"schedule": [T0, T1], "schedule_table": sched_table, "references": refs,
+                "heldout_ce": ce_held, "heldout_ce_uniform": ce_uniform})
     if args.params:
         rep.update({"params": os.path.basename(args.params)})
     else:
+        ce_train, ce_train_uniform = mean_ce(net, data)
         rep.update({"train_instances": len(data), "label_replicas": args.label_replicas,
                     "label_sweeps": args.label_sweeps, "label_s": label_ms / 1e3, "train_s": train_s,
-                    "train_curve": curve, "epochs": args.epochs})
+                    "train_curve": curve, "epochs": args.epochs, "train_ce": ce_train,
+                    "train_ce_uniform": ce_train_uniform})
     txt = json.dumps(rep)
     print(txt, flush=True)
     if args.out:

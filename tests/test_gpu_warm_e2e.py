@@ -28,7 +28,7 @@ def test_warm_start_pipeline(W):
     train = W.make_instances(40, 10000)
     data, _ = W.label_data(train, 64, 300, 200.0, 0.5, 1)
     assert len(data) >= 35                         # best states are tours (penalty 2 w_max)
-    for X, lab, m in data:
+    for X, lab, m, _ in data:
         assert X.shape == (m, 16) and sorted(lab.tolist()) == list(range(m))
     net, curve, _ = W.train(data, epochs=6, batch=8, lr=3e-3)
     assert np.isfinite(curve).all() and curve[-1] <= curve[0] + 1e-3
