@@ -54,6 +54,11 @@ def parse():
                     help="only copy BYTES of device memory once (reference run for the HBM byte counters)")
     ap.add_argument("--aux", action="store_true",
                     help="instead: time the MFMA energy refresh and the warm-start network step (one JSON line each)")
+    ap.add_argument("--mfma-only", action="store_true",
+                    help="with --aux: only the two MFMA users (for counter runs)")
+    ap.add_argument("--segments", default="",
+                    help="instead: one anneal of the workload cut at these sweeps (e.g. 0,500,1000,4000), one "
+                         "JSON line per piece with its sweep-kernel time and counts (the schedule's regimes)")
     return ap.parse_args()
 
 
@@ -100,6 +105,16 @@ def aux_measurements(args):
                           "kernel": "k_energy_refresh", "config": {"workload": name, "m": q.m, "states": w.replicas},
                           "ms_per_call": ms, "ops_per_call": ops, "peak": PEAK_INT8_OPS,
                           "frac": ops / (ms * 1e-3) / PEAK_INT8_OPS}), flush=True)
+    if not args.mfma_only:
+        extra_measurements()
+    mlp_measurement()
+
+
+def extra_measurements():
+    """Time to result with UAVQ_STOP_FROZEN, and parallel tempering beside the
+    plain anneal of the same replica-sweeps."""
+    import numpy as np
+    from paper_2608_25376_amd import inputs, uavq
     # time to result with UAVQ_STOP_FROZEN: the same anneals, identical outputs, frozen sweeps skipped
     # (a wall time, not a throughput: the skipped sweeps are not evaluated)
     for name in ("grid8x8_nofly0.1", "grid12x12"):
@@ -139,7 +154,14 @@ def aux_measurements(args):
     row["value"] = attempts / (row["interval10_ms"] * 1e-3)
     row["plain_value"] = attempts / (row["plain_ms"] * 1e-3)
     print(json.dumps(row), flush=True)
-    # warm-start network: 32 fields of 10x10 (about 85 free cells each)
+
+
+def mlp_measurement():
+    """One forward+backward step of the warm-start network on 32 fields of
+    10x10 (about 85 free cells each), eager and replayed from a HIP graph."""
+    import numpy as np
+    import torch
+    from paper_2608_25376_amd import inputs, uavq
     from paper_2608_25376_amd import warmstart
     grids = inputs.batch(32, seed=1, side=10, density_hi=0.2, first_id=10000)
     feats, steps, labels = [], [], []
@@ -182,8 +204,42 @@ def aux_measurements(args):
 
 # Sources of the sweep kernels; an HBM-traffic record applies only to the
 # build whose sources hash to the value stored with it.
-KERNEL_SOURCES = ["paper_2608_25376_amd/csrc/uavq_kernels.hip", "paper_2608_25376_amd/csrc/uavq_device.h",
-                  "paper_2608_25376_amd/csrc/uavq_internal.h"]
+KERNEL_SOURCES = ["paper_2608_25376_amd/csrc/uavq_kernels.hip", "paper_2608_25376_amd/csrc/uavq_sweep_chunk.hip",
+                  "paper_2608_25376_amd/csrc/uavq_device.h", "paper_2608_25376_amd/csrc/uavq_internal.h"]
+
+
+def segment_measurements(args):
+    """One anneal of the workload run as consecutive segments of its schedule
+    (uavq_anneal_segment, resumed): per piece, the sweep kernels' time (HIP
+    events on their stream) and the attempts, accepts and draws it added."""
+    import numpy as np
+    import torch
+    from paper_2608_25376_amd import inputs, uavq
+    w = inputs.workload(args.workload)
+    cuts = [int(v) for v in args.segments.split(",")]
+    assert cuts[0] == 0 and cuts[-1] == w.sweeps and cuts == sorted(cuts), "cuts must run from 0 to the sweeps"
+    qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in w.grids]
+    plan = uavq.Plan(qs, [g.inst_id for g in w.grids], w.replicas, w.sweeps, w.T0, w.T1, w.seed,
+                     generic_chunk=args.generic_chunk)
+    plan.upload()
+    out = plan.alloc_outputs()
+    plan.set_timing(True)
+    torch.cuda.synchronize()
+    n_vars = sum(q.n_vars for q in qs)
+    acc0 = drw0 = 0
+    for a, b in zip(cuts[:-1], cuts[1:]):
+        plan.anneal(out=out, s_begin=a, s_end=b, resume=a > 0)
+        torch.cuda.synchronize()
+        ms = plan.sweep_ms()
+        acc, drw = int(out.accepts.sum()), int(out.draws.sum())
+        att = float(n_vars * w.replicas * (b - a))
+        T_a = w.T0 * (w.T1 / w.T0) ** (a / max(w.sweeps - 1, 1))
+        print(json.dumps({"workload": w.name, "sweeps": [a, b], "T_first": T_a, "kernel_ms": ms,
+                          "ms_per_sweep": ms / max(b - a, 1), "attempts": att, "attempts_per_s": att / (ms * 1e-3),
+                          "accepts": acc - acc0, "draws": drw - drw0,
+                          "kernel": "+".join(k for k in (plan.kernel_name(c) for c in range(1, uavq.CHUNK_CLASSES + 1)) if k)}),
+              flush=True)
+        acc0, drw0 = acc, drw
 
 
 def kernel_source_sha256():
@@ -280,6 +336,9 @@ def main():
         return
     if args.aux:
         aux_measurements(args)
+        return
+    if args.segments:
+        segment_measurements(args)
         return
     w = inputs.workload(args.workload)
     dense = args.kernel == "dense"

@@ -178,8 +178,8 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
 
 /* Launch shape chosen by uavq_autotune (never changes results). */
 typedef struct {
-    int32_t waves_per_block[7];  /* per chunk class c = ceil(m/64) (index 0 unused); 0 = default;
-                                    classes 4..6 run at most 4 per block */
+    int32_t waves_per_block[10]; /* per chunk class (index 0 unused); 0 = default; classes 4..9
+                                    run at most 4 per block */
     uint32_t variant_flags;      /* 0 or UAVQ_VARIANT_ROWMASK / _NOPRODUCER / _GENERIC */
     float trial_ms;              /* measured time of the chosen shape (trial run) */
 } uavq_tune;
@@ -217,7 +217,8 @@ typedef struct {
 } uavq_plan_info_t;
 int uavq_plan_info(const uavq_plan *plan, uavq_plan_info_t *info);
 /* Name of the sweep kernel that uavq_anneal_batch launches for the
- * instances of chunk class cls (1: m <= 64, 2: m <= 128, ..., 6: m <= 384), for
+ * instances of chunk class cls (1: m <= 64, 2: m <= 128, ..., 9: m <= 576; a field
+ * whose costs exceed 255 runs in class 7 or above, which read 16-bit costs), for
  * profiling and reports: "" if the class is empty, NULL on error (cls out of
  * range, or no HIP device to decide the launch shape on).  The string is
  * static. */

@@ -7,9 +7,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuavq.so")
-SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_sweep_chunk.hip", "uavq_refresh.hip", "uavq_warm.hip",
-           "uavq_pt.hip"]
-HEADERS = ["uavq_internal.h", "uavq_device.h", os.path.join("..", "..", "include", "uavq.h")]
+SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_sweep_chunk.hip", "uavq_sweep_big.hip", "uavq_refresh.hip",
+           "uavq_warm.hip", "uavq_pt.hip"]
+HEADERS = ["uavq_internal.h", "uavq_device.h", "uavq_factored.h", os.path.join("..", "..", "include", "uavq.h")]
 ARCH = os.environ.get("UAVQ_OFFLOAD_ARCH", "gfx950")
 
 
@@ -46,7 +46,8 @@ def build(force: bool = True, verbose: bool = False) -> str:
     # chunks (m <= 384), or the lane's arrays move to scratch memory; the other
     # kernels of the file compile to the same code with or without this.
     per_file = {"uavq_kernels.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
-                "uavq_sweep_chunk.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
+                "uavq_sweep_chunk.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
+                "uavq_sweep_big.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
     objs, cmds = [], []
     for s in SOURCES:
         src = os.path.join(CSRC, s)

@@ -111,7 +111,7 @@ int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out) {
         }
     }
     q->wmax = wmax;
-    if (wmax > 255) { delete q; return set_error(UAVQ_ETOOBIG, "qubo_build: w_max %d > 255", wmax); }
+    if (wmax > 65535) { delete q; return set_error(UAVQ_ETOOBIG, "qubo_build: w_max %d > 65535", wmax); }
     int32_t P = g->penalty ? g->penalty : 2 * wmax;
     if (P <= wmax) { delete q; return set_error(UAVQ_EINVAL, "qubo_build: penalty %d <= w_max %d", P, wmax); }
     // Every local field and energy change the kernels form is an int32: with
@@ -123,18 +123,23 @@ int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out) {
     }
     q->P = P;
     q->c0 = 2LL * P * m;
-    q->D.resize((size_t)m * m);
-    q->ddep.resize(m);
+    q->D16.resize((size_t)m * m);
+    q->ddep16.resize(m);
     for (int32_t c = 0; c < m; c++) {
-        q->ddep[c] = (uint8_t)q->W[c + 1];
-        for (int32_t c2 = 0; c2 < m; c2++) q->D[(size_t)c * m + c2] = (uint8_t)q->W[(size_t)(c + 1) * (m + 1) + c2 + 1];
+        q->ddep16[c] = (uint16_t)q->W[c + 1];
+        for (int32_t c2 = 0; c2 < m; c2++)
+            q->D16[(size_t)c * m + c2] = (uint16_t)q->W[(size_t)(c + 1) * (m + 1) + c2 + 1];
+    }
+    if (wmax <= 255) {   // the byte copies the LDS-resident kernels and the MFMA refresh read
+        q->D.assign(q->D16.begin(), q->D16.end());
+        q->ddep.assign(q->ddep16.begin(), q->ddep16.end());
     }
     q->b.resize(q->N);
     for (int32_t t = 1; t <= m; t++)
         for (int32_t c = 0; c < m; c++) {
             int32_t v = -2 * P;
-            if (t == 1) v += q->ddep[c];
-            if (t == m && q->closed) v += q->ddep[c];
+            if (t == 1) v += q->ddep16[c];
+            if (t == m && q->closed) v += q->ddep16[c];
             q->b[(size_t)(t - 1) * m + c] = v;
         }
     if (g->flags & UAVQ_DENSE) {
@@ -161,7 +166,7 @@ int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out) {
                 for (int32_t dt = -1; dt <= 1; dt += 2) {
                     int32_t t2 = t + dt;
                     if (t2 < 0 || t2 >= m) continue;
-                    for (int32_t c2 = 0; c2 < m; c2++) row[t2 * m + c2] += (int16_t)q->D[(size_t)c * m + c2];
+                    for (int32_t c2 = 0; c2 < m; c2++) row[t2 * m + c2] += (int16_t)q->D16[(size_t)c * m + c2];
                 }
             }
     }
@@ -230,7 +235,7 @@ int uavq_energy_eval(const uavq_qubo *q, const uint32_t *x, int64_t n, int64_t *
             for (int32_t c : ones) {
                 e += q->b[(size_t)(t - 1) * m + c];
                 colcnt[c]++;
-                for (int32_t cp : prev) e += q->D[(size_t)cp * m + c];
+                for (int32_t cp : prev) e += q->D16[(size_t)cp * m + c];
             }
             prev.swap(ones);
         }
@@ -255,14 +260,14 @@ int uavq_decode_path(const uavq_qubo *q, const uint32_t *x, int32_t *path, int64
         }
         if (order[t - 1] < 0) return set_error(UAVQ_EINFEASIBLE, "decode_path: step %d empty", t);
     }
-    int64_t total = q->ddep[order[0]];
+    int64_t total = q->ddep16[order[0]];
     path[0] = q->depot;
     for (int32_t t = 0; t < m; t++) {
         path[t + 1] = q->F[order[t]];
-        if (t > 0) total += q->D[(size_t)order[t - 1] * m + order[t]];
+        if (t > 0) total += q->D16[(size_t)order[t - 1] * m + order[t]];
     }
     if (q->closed) {
-        total += q->ddep[order[m - 1]];
+        total += q->ddep16[order[m - 1]];
         path[m + 1] = q->depot;
     } else {
         path[m + 1] = -1;
@@ -357,6 +362,14 @@ int uavq_pt_ladder(double T_hot, double T_cold, int32_t K, double *T, int32_t *D
 }
 
 // ------------------------------------------------------------------ plans --
+
+// Chunk class of an instance: ceil(m/64), and at least kByteChunks + 1 when
+// its costs do not fit a byte (only those classes read 16-bit costs).
+static int inst_class(const uavq_qubo *q, bool dense) {
+    if (dense) return 1;
+    const int c = (q->m + 63) / 64;
+    return q->wmax > 255 ? std::max(c, kByteChunks + 1) : c;
+}
 
 static int default_waves_per_block(int chunks) {
     (void)chunks;
@@ -507,8 +520,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         pl->waves_per_block[cls] = wpb;
         pl->class_begin[cls] = (int32_t)pl->items.size();
         for (int32_t i : order) {
-            int32_t chunks = dense ? 1 : (q[i]->m + 63) / 64;
-            if (chunks != cls) continue;
+            if (inst_class(q[i], dense) != cls) continue;
             for (int32_t r0 = 0; r0 < R; r0 += wpb) pl->items.push_back({i, r0, std::min(wpb, R - r0), 0});
         }
     }
@@ -524,8 +536,10 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         d.state_words = qi->m * qi->row_words;
         d.nrep = R;
         d.c0 = qi->c0;
-        d.d_off = (int64_t)off;     off = align_up(off + qi->D.size(), 16);
-        d.ddep_off = (int64_t)off;  off = align_up(off + qi->ddep.size(), 256);
+        const size_t cb = inst_class(qi, dense) > kByteChunks ? 2 : 1;   // bytes per cost entry
+        // 16-bit matrices are read from global memory, lanes past m up to 64 kMaxChunks entries beyond the end
+        d.d_off = (int64_t)off;     off = align_up(off + cb * qi->D16.size() + (cb == 2 ? 2 * 64 * kMaxChunks : 0), 16);
+        d.ddep_off = (int64_t)off;  off = align_up(off + cb * qi->ddep16.size(), 256);
         if (dense) {
             const size_t Np = ((size_t)qi->N + 31) / 32 * 32;
             d.J_off = (int64_t)off;     off = align_up(off + qi->J.size() * 2, 256);
@@ -539,7 +553,9 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         d.rep_base = pl->rep_offset[i];
         d.state_off = pl->state_offset[i];
         d.inst_id = inst_ids[i];
-        d.chunks = (qi->m + 63) / 64;
+        d.chunks = inst_class(qi, dense);
+        d.wide = qi->wmax > 255 ? 1 : 0;
+        d.pad_ = 0;
         const int32_t sj = sched_of[i];
         d.sched_row = sched_row[sj];
         d.sched_step = sched_rows[sj] > 1 ? 1 : 0;
@@ -562,8 +578,13 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     for (int32_t i = 0; i < n_inst; i++) {
         const uavq_qubo *qi = q[i];
         const InstDesc &d = pl->desc[i];
-        std::memcpy(B + d.d_off, qi->D.data(), qi->D.size());
-        std::memcpy(B + d.ddep_off, qi->ddep.data(), qi->ddep.size());
+        if (d.chunks > kByteChunks) {
+            std::memcpy(B + d.d_off, qi->D16.data(), 2 * qi->D16.size());
+            std::memcpy(B + d.ddep_off, qi->ddep16.data(), 2 * qi->ddep16.size());
+        } else {
+            std::memcpy(B + d.d_off, qi->D.data(), qi->D.size());
+            std::memcpy(B + d.ddep_off, qi->ddep.data(), qi->ddep.size());
+        }
         if (dense) {
             std::memcpy(B + d.J_off, qi->J.data(), qi->J.size() * 2);
             std::memcpy(B + d.b_off, qi->b.data(), qi->b.size() * 4);

@@ -12,8 +12,11 @@ typedef struct ihipStream_t *hipStream_t_opaque;
 namespace uavq {
 
 // Largest number of 64-column chunks a replica row may span in the factored
-// kernel (m <= 64 * kMaxChunks).
-constexpr int kMaxChunks = 6;
+// kernel (m <= 64 * kMaxChunks).  Classes 1..kByteChunks keep the cost matrix
+// as bytes in LDS; the classes above read 16-bit costs from global memory
+// (fields past 19x19, and every field with a cost above 255).
+constexpr int kMaxChunks = 9;
+constexpr int kByteChunks = 6;
 constexpr int kMaxM = 64 * kMaxChunks;
 constexpr int kWideMaxWaves = 4;   // waves per block of the kernels of classes 4..kMaxChunks
 
@@ -24,8 +27,8 @@ struct InstDesc {
     int32_t m, P, closed, row_words;
     int32_t state_words, nrep;
     int64_t c0;
-    int64_t d_off;      // byte offset of D (m*m uint8, row-major)
-    int64_t ddep_off;   // byte offset of the start-cell costs (m uint8)
+    int64_t d_off;      // byte offset of D (m*m, row-major): uint8, or uint16 for classes above kByteChunks
+    int64_t ddep_off;   // byte offset of the start-cell costs (m entries, same type)
     int64_t J_off;      // byte offset of the dense J (N*N int16) or -1
     int64_t Jlimb_off;  // byte offset of the J limbs (two Np*Np int8: J & 127, J >> 7) or -1
     int64_t b_off;      // byte offset of b (N int32) or -1
@@ -37,6 +40,8 @@ struct InstDesc {
     // sched_row + s * sched_step (step 0: a constant temperature, one row)
     int32_t sched_row, sched_step;
     float tl2_a, tl2_b; // T_s ln 2 ~= exp2(tl2_a + tl2_b s): starting guess for acceptance cuts
+    int32_t wide;       // a cost exceeds 255 (no byte copy of D for the MFMA energy check)
+    int32_t pad_;
 };
 
 // One workgroup's share: replicas rep0 .. rep0+nrep-1 of instance inst.
@@ -87,8 +92,10 @@ struct uavq_qubo {
     int64_t c0;
     std::vector<int32_t> F;      // m grid indices
     std::vector<int32_t> W;      // (m+1)^2 costs over [start, F...]
-    std::vector<uint8_t> D;      // m*m costs between free cells
-    std::vector<uint8_t> ddep;   // m costs start -> free cell
+    std::vector<uint8_t> D;      // m*m costs between free cells as bytes (empty when w_max > 255)
+    std::vector<uint8_t> ddep;   // m costs start -> free cell as bytes (empty when w_max > 255)
+    std::vector<uint16_t> D16;   // the same costs, 16-bit (always)
+    std::vector<uint16_t> ddep16;
     std::vector<int32_t> b;      // N linear terms
     std::vector<int16_t> J;      // N*N dense couplings (optional)
 };
@@ -138,6 +145,8 @@ extern "C" void plan_destroy_events(uavq_plan *pl);   // also releases a cached 
 namespace uavq {
 // the block-tested chunked sweep for nj = 2, 3 chunks (uavq_sweep_chunk.hip); NULL otherwise
 const void *chunk_sweep_kernel(int nj, bool stop);
+// the 16-bit-cost sweep of classes 7..9 (uavq_sweep_big.hip); NULL otherwise
+const void *big_sweep_kernel(int nj, bool stop);
 int launch_anneal(const uavq_plan *plan, const KArgs &a, void *stream, int64_t *check_E);
 int launch_dense(const uavq_plan *plan, const KArgs &a, hipStream_t_opaque st);
 int launch_energy_refresh(const uint32_t *d_states, int64_t n, int64_t *d_E, const uint8_t *d_D, const uint8_t *d_dep,

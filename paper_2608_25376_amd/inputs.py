@@ -85,6 +85,12 @@ def workload(name: str) -> Workload:
     if name == "grid19x19":
         return Workload(name, [grid(19, 19)], 4096, 1000, 200.0, 0.5, 1,
                         "19x19, no obstacles, 360 free cells, 129600 vars (the largest field with 8-bit costs)")
+    if name == "grid20x20":
+        return Workload(name, [grid(20, 20)], 4096, 1000, 200.0, 0.5, 1,
+                        "20x20, no obstacles, 399 free cells, 159201 vars, costs up to 269 (16-bit)")
+    if name == "grid24x24":
+        return Workload(name, [grid(24, 24)], 4096, 1000, 200.0, 0.5, 1,
+                        "24x24, no obstacles, 575 free cells, 330625 vars, costs up to 325 (16-bit)")
     if name == "batch256":
         return Workload(name, batch(256, 1), 256, 2000, 200.0, 0.5, 1,
                         "256 instances, side U{4..10}, density U[0,0.2]")

@@ -26,7 +26,7 @@ VARIANT_NOPRODUCER = 0x80
 VARIANT_GENERIC = 0x400
 STOP_FROZEN = 0x100
 REDUCE_AT_END = 0x200
-CHUNK_CLASSES = 6          # sweep kernel classes by ceil(m / 64); m <= 384
+CHUNK_CLASSES = 9          # sweep kernel classes by ceil(m / 64), 16-bit costs from class 7; m <= 576
 
 OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
 
@@ -51,7 +51,7 @@ class _QuboInfo(C.Structure):
 
 class Tune(C.Structure):
     """Launch shape chosen by autotune (per chunk class c = ceil(m/64))."""
-    _fields_ = [("waves_per_block", C.c_int32 * 7), ("variant_flags", C.c_uint32), ("trial_ms", C.c_float)]
+    _fields_ = [("waves_per_block", C.c_int32 * 10), ("variant_flags", C.c_uint32), ("trial_ms", C.c_float)]
 
     def __repr__(self):
         return (f"Tune(waves_per_block={list(self.waves_per_block)[1:]}, variant={self.variant_flags:#x}, "

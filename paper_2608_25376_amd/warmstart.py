@@ -201,6 +201,57 @@ def warm_init(net, plan, qs, frac, s0, stream=None):
     return init, (time.perf_counter() - t0) * 1e3
 
 
+def bits_init(plan, qs, probs, density, frac, seed, uniform=False):
+    """Seeds for the density study, drawn on the host: in each instance the
+    first frac of the replicas start from independent bits, x_{t,c} = 1 with
+    probability min(1, density p(t|c)), p the network's marginal of cell c over
+    the steps (or 1/m with ``uniform``), so about density ones per step."""
+    import torch
+    rng = np.random.default_rng(seed)
+    words = np.zeros(plan.total_state_words, np.uint32)
+    seeded = np.zeros(plan.total_replicas, np.uint8)
+    n = int(round(frac * plan.replicas))
+    row = 0
+    for i, q in enumerate(qs):
+        m = q.m
+        p = np.full((m, m), 1.0 / m) if uniform else probs[row:row + m, :m]
+        row += m
+        pr = np.minimum(1.0, density * p.T)          # [step][cell]
+        x = (rng.random((n, m, m)) < pr[None]).astype(np.uint8)
+        base = plan.state_offset[i]
+        words[base:base + n * q.state_words] = uavq.pack_states(x.reshape(n, -1), m).reshape(-1)
+        seeded[plan.rep_offset[i]:plan.rep_offset[i] + n] = 1
+    return {"init_states": torch.from_numpy(words.view(np.int32)).cuda(), "seeded": torch.from_numpy(seeded).cuda()}
+
+
+def density_study(grids, net, R, S, T0, T1, seed, densities=(3.0, 4.0, 5.0, 6.0, 8.0, 12.0), log=None):
+    """The annealer at one budget from: random bits (Bernoulli 1/2), tours
+    sampled from the network (half of the replicas), and sparse bits at
+    several densities biased by the network's marginals or uniform (every
+    replica); the best energies are compared with the best of all these runs."""
+    import torch
+    qs = _qubos(grids)
+    X = torch.from_numpy(np.concatenate([uavq.mlp_features(q) for q in qs])).cuda()
+    msteps = torch.from_numpy(np.concatenate([np.full(q.m, q.m, np.int32) for q in qs])).cuda()
+    probs = net.forward(X, msteps).cpu().numpy()
+    runs = {}
+    plan, out, _ = _anneal(qs, grids, R, S, T0, T1, seed)
+    runs["random bits"] = out.inst_best_E.cpu().numpy().copy()
+    init, _ = warm_init(net, plan, qs, 0.5, 0)
+    _, out, _ = _anneal(qs, grids, R, S, T0, T1, seed, init=init, plan=plan)
+    runs["sampled tours (half)"] = out.inst_best_E.cpu().numpy().copy()
+    for uniform in (False, True):
+        for dens in densities:
+            init = bits_init(plan, qs, probs, dens, 1.0, seed + 17, uniform=uniform)
+            _, out, _ = _anneal(qs, grids, R, S, T0, T1, seed, init=init, plan=plan)
+            runs[f"{'uniform' if uniform else 'network'} bits, {dens:g} per step"] = out.inst_best_E.cpu().numpy().copy()
+            if log:
+                log(f"density study: {'uniform' if uniform else 'network'} {dens}")
+    best = np.min(np.stack(list(runs.values())), 0)
+    return {k: {"fraction_within_1pct": float(np.mean(100 * E <= 101 * best)),
+                "mean_gap": float(np.mean(E / best - 1.0))} for k, E in runs.items()}
+
+
 def ttt(grids, net, R, ladder, T0, T1, seed, T_warm, frac=0.5, ref_sweeps=8000, single=True, log=None,
         refs=()):
     """``refs``: further reference runs (T0, T1, sweeps) whose energies enter the best known."""
@@ -317,7 +368,7 @@ def mean_ce(net, data, batch=64):
         X = torch.from_numpy(np.concatenate([d[0] for d in sel])).cuda()
         lab = torch.from_numpy(np.concatenate([d[1] for d in sel])).cuda()
         msteps = torch.from_numpy(np.concatenate([np.full(d[2], d[2], np.int32) for d in sel])).cuda()
-        tot += float(net.loss_grad(X, msteps, lab).cpu()[0])
+        tot += float(net.loss_grad(X, msteps, lab)[0].cpu()[0])
         rows += X.shape[0]
         uni += float(sum(d[2] * np.log(d[2]) for d in sel))
     return tot / rows, uni / rows
@@ -356,6 +407,9 @@ def main():
     ap.add_argument("--params", default="", help="network parameters saved by an earlier run (.npy): "
                     "skip labelling and training (needs --schedule T0,T1)")
     ap.add_argument("--save-labels", default="", help="write the training labels to this .npz")
+    ap.add_argument("--labels-only", action="store_true", help="stop after labelling (with --save-labels)")
+    ap.add_argument("--density-study", type=int, default=0, metavar="S",
+                    help="also run the initial-density study on the held-out set at S sweeps")
     ap.add_argument("--merge", default="", help="comma-separated reports of earlier runs: combine their seeds "
                     "and write the medians to --out (no GPU work)")
     ap.add_argument("--out", default="")
@@ -391,6 +445,8 @@ def main():
         log(f"labelled {len(data)}/{len(train_grids)} training instances in {label_ms / 1e3:.1f} s")
         if args.save_labels:
             save_labels(args.save_labels, data)
+        if args.labels_only:
+            return
         net, curve, train_s = train(data, epochs=args.epochs, batch=args.batch, lr=args.lr, log=log)
     ladder = [int(v) for v in args.ladder.split(",")]
     constant = T0 == T1
@@ -427,6 +483,10 @@ def main():
     rep["median"] = seed_medians(rep["per_seed"])
     rep.update({"schedule": [T0, T1], "schedule_table": sched_table, "references": refs,
                 "heldout_ce": ce_held, "heldout_ce_uniform": ce_uniform})
+    if args.density_study:
+        rep["density_study"] = {"sweeps": args.density_study, "replicas": args.replicas,
+                                "runs": density_study(held, net, args.replicas, args.density_study, T0, T1, seed,
+                                                      log=log)}
     if args.params:
         rep.update({"params": os.path.basename(args.params)})
     else:

@@ -125,8 +125,13 @@ def test_validation_errors(U):
     with pytest.raises(U.UavqError) as e:
         U.qubo_build(7, 7, penalty=Pd + 1, dense=True)
     assert e.value.code == U.ETOOBIG
+    q30 = U.qubo_build(30, 30)                   # w_max = 410: 16-bit costs
+    assert q30.w_max == 410 and q30.m == 899
     with pytest.raises(U.UavqError) as e:
-        U.qubo_build(30, 30)                     # w_max > 255
+        U.Plan([q30], [0], 4, 10, 10.0, 1.0)     # m = 899 > 576
+    assert e.value.code == U.ETOOBIG
+    with pytest.raises(U.UavqError) as e:
+        U.qubo_build(1, 300, cost_scale=300)     # a cost above 65535
     assert e.value.code == U.ETOOBIG
     q = U.qubo_build(3, 3)
     with pytest.raises(U.UavqError):
@@ -139,9 +144,14 @@ def test_validation_errors(U):
         U.Plan([q], [0], 4, 10, 10.0, 1.0, dense=True)   # dense kernel needs the dense J
     ok = U.Plan([U.qubo_build(19, 19)], [0], 4, 10, 10.0, 1.0)   # m = 360: the sixth chunk class
     assert ok.total_state_words == 4 * 360 * 12
-    big = U.qubo_build(20, 20, cost_scale=5)     # m = 399 > 384 (w_max 134 at this cost scale)
+    big = U.qubo_build(20, 20, cost_scale=5)     # m = 399 > 384 (w_max 134 at this cost scale): class 7
+    assert U.Plan([big], [0], 4, 10, 10.0, 1.0).total_state_words == 4 * 399 * 13
+    wide = U.qubo_build(20, 20)                  # w_max = 269 > 255: 16-bit costs, class 7
+    assert wide.w_max == 269
+    assert U.Plan([wide], [0], 4, 10, 10.0, 1.0).total_replicas == 4
+    huge = U.qubo_build(25, 25)                  # m = 624 > 576
     with pytest.raises(U.UavqError) as e:
-        U.Plan([big], [0], 4, 10, 10.0, 1.0)
+        U.Plan([huge], [0], 4, 10, 10.0, 1.0)
     assert e.value.code == U.ETOOBIG
 
 
@@ -173,11 +183,12 @@ def test_plan_kernel_name_without_device(U):
     q = U.qubo_build(3, 3, dense=True)
     p = U.Plan([q], [0], 4, 10, 10.0, 1.0)
     with pytest.raises(U.UavqError):
-        p.kernel_name(0)                          # classes are 1..6
+        p.kernel_name(0)                          # classes are 1..9
     with pytest.raises(U.UavqError):
-        p.kernel_name(7)
+        p.kernel_name(10)
     assert p.kernel_name(4) == ""                 # no instance with 192 < m <= 256
     assert p.kernel_name(6) == ""                 # no instance with 320 < m <= 384
+    assert p.kernel_name(9) == ""                 # no instance with 512 < m <= 576
     assert p.kernel_name(2) == ""                 # no instance with 64 < m <= 128
     pd = U.Plan([q], [0], 4, 10, 10.0, 1.0, dense=True)
     assert pd.kernel_name(1) == "k_sweep_dense"

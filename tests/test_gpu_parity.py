@@ -356,3 +356,49 @@ def test_block_tested_kernel_equals_generic(U, side, dens, inst):
     for k in ra:
         assert np.array_equal(ra[k], rb[k]), k
     assert np.array_equal(ra["check_E"], ra["final_E"])
+
+
+@pytest.mark.parametrize("rows,cols,dens,inst,scale,cls,kernel", [
+    (20, 20, 0.0, 90, 10, 7, "k_sweep_factored_big<7>"),     # m = 399, w_max = 269: 16-bit costs
+    (20, 20, 0.0, 91, 5, 7, "k_sweep_factored_big<7>"),      # m = 399, w_max = 134: class 7 by size alone
+    (22, 22, 0.0, 92, 10, 8, "k_sweep_factored_big<9>"),     # m = 483: class 8 runs in the nine-chunk build
+    (24, 24, 0.0, 93, 10, 9, "k_sweep_factored_big<9>"),     # m = 575, 330,625 variables
+    (1, 30, 0.0, 94, 10, 7, "k_sweep_factored_big<7>"),      # m = 29 but w_max = 290: 16-bit costs
+])
+def test_sixteen_bit_cost_fields(U, oracle_lib, rows, cols, dens, inst, scale, cls, kernel):
+    """Fields past 19x19 and fields whose travel costs exceed a byte: the
+    kernels of classes 7..9 (16-bit costs read from global memory) against the
+    oracle (coefficients from their definition) on two replicas started from
+    random tours over a short hot schedule; every replica's energy equals the
+    host evaluation of its final state."""
+    g = inputs.grid(rows, cols, dens, seed=2, inst=inst)
+    q0 = U.qubo_build(rows, cols, nofly=g.nofly, cost_scale=scale)
+    m = q0.m
+    R, S, T0, T1 = 6, 3, 150.0, 50.0
+    rng = np.random.default_rng(inst)
+    x0 = np.zeros((R, m * m), np.uint8)
+    for r in range(R):
+        X = np.zeros((m, m), np.uint8)
+        X[np.arange(m), rng.permutation(m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = np.ones(R, np.uint8)
+    say(f"case: 16-bit costs {rows}x{cols} scale={scale} m={m} w_max={q0.w_max} R={R} S={S}")
+    import torch
+    q = q0
+    plan = U.Plan([q], [g.inst_id], R, S, T0, T1, 3)
+    assert plan.kernel_name(cls) == kernel
+    plan.upload()
+    packed = U.pack_states(x0, m).reshape(-1)
+    out = plan.anneal(init_states=torch.from_numpy(packed.view(np.int32)).cuda(),
+                      seeded=torch.from_numpy(seeded).cuda())
+    torch.cuda.synchronize()
+    res = {k: getattr(out, k).cpu().numpy() for k in out.__dataclass_fields__}
+    gi = split(U, [q], plan, res)[0]
+    E_host = U.energy_eval(q, res["final_states"].view(np.uint32).reshape(R, q.state_words))
+    assert np.array_equal(E_host, gi["final_E"])
+    check_reduce(oracle_lib, gi, R, f"{rows}x{cols} reduce")
+    o = oracle_lib.OracleQubo(rows, cols, nofly=g.nofly, scale=scale, dense=False)
+    assert o.wmax == q.w_max and o.P == q.P
+    reps = [0, R - 1] if m > 100 else list(range(R))
+    orc = oracle_lib.anneal(o, S, T0, T1, 3, g.inst_id, reps, init_x=x0[reps], threads=2)
+    compare_replicas(gi, orc, reps, f"{rows}x{cols}")
