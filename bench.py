@@ -50,6 +50,8 @@ def parse():
     ap.add_argument("--autotune", action="store_true", help="choose the launch shape with uavq_autotune")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-replicas", type=int, default=0, help="oracle sample size (0 = auto)")
+    ap.add_argument("--concurrent", action="store_true",
+                    help="run the chunk classes' sweep kernels at the same time (UAVQ_CONCURRENT_CLASSES)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES of device memory once (reference run for the HBM byte counters)")
     ap.add_argument("--aux", action="store_true",
@@ -202,10 +204,16 @@ def mlp_measurement():
                       "frac": flops / (graph_ms * 1e-3) / PEAK_BF16_FLOPS}), flush=True)
 
 
-# Sources of the sweep kernels; an HBM-traffic record applies only to the
-# build whose sources hash to the value stored with it.
-KERNEL_SOURCES = ["paper_2608_25376_amd/csrc/uavq_kernels.hip", "paper_2608_25376_amd/csrc/uavq_sweep_chunk.hip",
-                  "paper_2608_25376_amd/csrc/uavq_device.h", "paper_2608_25376_amd/csrc/uavq_internal.h"]
+# Sources of each sweep kernel's translation unit; an HBM-traffic record
+# applies only to the build whose sources hash to the value stored with it.
+_CSRC = "paper_2608_25376_amd/csrc/"
+_COMMON = [_CSRC + "uavq_device.h", _CSRC + "uavq_kargs.h"]
+KERNEL_SOURCES = {
+    "k_sweep_chunk": [_CSRC + "uavq_sweep_chunk.hip"] + _COMMON,
+    "k_sweep_factored_big": [_CSRC + "uavq_sweep_big.hip", _CSRC + "uavq_factored.h"] + _COMMON,
+    "k_sweep_dense": [_CSRC + "uavq_refresh.hip", _CSRC + "uavq_internal.h"] + _COMMON,
+    "k_sweep": [_CSRC + "uavq_kernels.hip", _CSRC + "uavq_factored.h", _CSRC + "uavq_internal.h"] + _COMMON,
+}
 
 
 def segment_measurements(args):
@@ -242,9 +250,11 @@ def segment_measurements(args):
         acc0, drw0 = acc, drw
 
 
-def kernel_source_sha256():
+def kernel_source_sha256(kernel):
+    """sha256 over the sources that build `kernel` (longest matching name prefix)."""
+    key = max((k for k in KERNEL_SOURCES if kernel.startswith(k)), key=len)
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[key]:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -254,14 +264,14 @@ def recorded_traffic(kernel, workload):
     """HBM bytes per launch from the committed counter summary of this kernel
     and workload (FETCH_SIZE + WRITE_SIZE, scaled by a copy of known size), or
     None if there is none or the kernel sources changed since it was taken."""
-    name = re.sub(r"[^A-Za-z0-9_.]+", "_", f"{kernel}_{workload}_traffic").strip("_") + ".md"
+    name = re.sub(r"[^A-Za-z0-9.]+", "_", f"{kernel}_{workload}_traffic").strip("_") + ".md"
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     txt = open(path).read()
     sha = re.search(r"^source_sha256:\s*([0-9a-f]{64})\s*$", txt, re.M)
     val = re.search(r"^hbm_bytes_per_launch:\s*([0-9.eE+]+)\s*$", txt, re.M)
-    if not sha or not val or sha.group(1) != kernel_source_sha256():
+    if not sha or not val or sha.group(1) != kernel_source_sha256(kernel):
         return None
     return float(val.group(1))
 
@@ -353,7 +363,7 @@ def main():
     plan = uavq.Plan(qs, ids, w.replicas, w.sweeps, w.T0, w.T1, w.seed, dense=dense,
                      waves_per_block=args.waves_per_block, rowmask=args.rowmask, persistent=args.persistent,
                      no_producer=args.no_producer, generic_chunk=args.generic_chunk,
-                     graph=args.graph, tune=tune)
+                     graph=args.graph, tune=tune, concurrent=args.concurrent)
     plan.upload(stream=stream if args.graph else None)
     out = plan.alloc_outputs()
     torch.cuda.synchronize()
@@ -382,6 +392,8 @@ def main():
 
     n_vars = sum(q.n_vars for q in qs)
     attempts = float(sum(q.n_vars for q in qs) * w.replicas * w.sweeps)
+    counted = int(out.attempts.cpu().numpy().astype(np.uint64).sum())
+    assert counted == int(attempts), f"attempts counter {counted} != replicas x sweeps x N = {int(attempts)}"
     acc = out.accepts.cpu().numpy().astype(np.float64)
     drw = out.draws.cpu().numpy().astype(np.float64)
     m_per_rep = np.concatenate([np.full(w.replicas, q.m) for q in qs]).astype(np.float64)
@@ -409,6 +421,7 @@ def main():
                    "n_vars": n_vars, "replicas": w.replicas, "sweeps": w.sweeps, "T0": w.T0, "T1": w.T1,
                    "seed": w.seed, "kernel": args.kernel, "persistent": args.persistent, "graph": args.graph,
                    "no_producer": args.no_producer, "generic_chunk": args.generic_chunk,
+                   "concurrent": args.concurrent,
                    "tune": repr(tune) if tune is not None else None, "attempts_per_step": attempts,
                    "accept_rate": float(acc.sum() / attempts), "draw_rate": float(drw.sum() / attempts),
                    "best_E": [int(v) for v in out.inst_best_E.cpu().numpy()[:4]]},

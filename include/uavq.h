@@ -53,7 +53,8 @@ enum {
     UAVQ_ENOMEM = -2,       /* host allocation failed */
     UAVQ_EHIP = -3,         /* a HIP runtime call failed (message names it) */
     UAVQ_ETOOBIG = -4,      /* the instance exceeds a kernel's limits */
-    UAVQ_EINFEASIBLE = -5   /* a state is not a permutation matrix */
+    UAVQ_EINFEASIBLE = -5,  /* a state is not a permutation matrix */
+    UAVQ_EINVARIANT = -6    /* an energy kept incrementally differs from its recomputation */
 };
 
 /* Message for the last error on this thread ("" if none).  Static storage. */
@@ -172,6 +173,10 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
 #define UAVQ_VARIANT_GENERIC 0x400u /* 64 < m <= 192: the generic chunked walk (every step walked) instead
                                       of the kernel that first tests blocks of four steps whose steps
                                       each hold one cell (a schedule choice; same results) */
+#define UAVQ_CONCURRENT_CLASSES 0x800u /* the sweep kernels of different chunk classes run at the same
+                                      time (the first on the caller's stream, the others on streams the
+                                      plan owns, forked and joined with events), so one class's blocks
+                                      fill the CUs that another's tail leaves idle.  Same results. */
 #define UAVQ_REDUCE_AT_END 0x200u  /* uavq_anneal_segment fills the per-instance outputs (inst_best_*)
                                       only in a segment that ends the schedule (s_end = S); earlier
                                       segments leave them untouched.  Per-replica outputs are unchanged. */
@@ -251,6 +256,10 @@ typedef struct {              /* device outputs, caller-owned; NULL = not wanted
     int32_t *inst_best_sweep;
     uint32_t *inst_best_state;/* total over instances of state_words */
     int64_t *check_E;         /* total_replicas: E(final state) recomputed by the refresh */
+    uint64_t *attempts;       /* total_replicas: flips attempted, N per sweep the replica ran
+                                 (sweeps max(start_sweep, s_begin) .. s_end-1); carried on resume
+                                 like accepts.  A replica stopped by UAVQ_STOP_FROZEN still counts
+                                 the sweeps it skipped: every site of them is rejected. */
 } uavq_anneal_out;
 
 /* anneal_batch -- single-flip Metropolis annealing of every replica:
@@ -285,6 +294,23 @@ int uavq_anneal_batch(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const 
  * a range outside [0, S] or any argument anneal_batch rejects. */
 int uavq_anneal_segment(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
                         const uavq_anneal_out *out, int32_t s_begin, int32_t s_end, int32_t resume, void *stream);
+
+/* anneal_checked -- anneal_batch with periodic invariant checks: the schedule
+ * runs in pieces of refresh_every sweeps (anneal_segment, resumed), and after
+ * each piece the MFMA refresh recomputes the energy of eqs. (3)-(6) from every
+ * replica's working state and compares it with the energy the sweep kernels
+ * kept by adding the dE of accepted flips.  d_violations (device, caller-owned,
+ * total_replicas uint32, cleared by the call) counts each replica's
+ * mismatching pieces; *n_violations (host) receives their sum.  out->check_E
+ * is required (it holds the last recomputation).  The outputs equal those of
+ * anneal_batch bit for bit.  Synchronous: the call waits for `stream`.
+ * Errors: UAVQ_EINVARIANT when any piece mismatched (outputs still written);
+ * UAVQ_EINVAL for refresh_every < 1, a missing buffer or a graph-mode plan;
+ * UAVQ_ETOOBIG for fields the refresh kernel does not take (m > 384 or costs
+ * above 255). */
+int uavq_anneal_checked(const uavq_plan *plan, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
+                        const uavq_anneal_out *out, int32_t refresh_every, uint32_t *d_violations,
+                        uint64_t *n_violations, void *stream);
 
 /* Autotuner: times anneal_batch launch shapes (replicas per workgroup per
  * chunk class, m <= 64 kernel variant) on a short trial of trial_sweeps

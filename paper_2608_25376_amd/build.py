@@ -9,7 +9,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuavq.so")
 SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_sweep_chunk.hip", "uavq_sweep_big.hip", "uavq_refresh.hip",
            "uavq_warm.hip", "uavq_pt.hip"]
-HEADERS = ["uavq_internal.h", "uavq_device.h", "uavq_factored.h", os.path.join("..", "..", "include", "uavq.h")]
+HEADERS = ["uavq_internal.h", "uavq_kargs.h", "uavq_device.h", "uavq_factored.h", os.path.join("..", "..", "include", "uavq.h")]
 ARCH = os.environ.get("UAVQ_OFFLOAD_ARCH", "gfx950")
 
 

@@ -4,7 +4,7 @@
 
 #include <cstdint>
 
-#include "uavq_internal.h"
+#include "uavq_kargs.h"
 
 #define UAVQ_HIP(call)                                                                   \
     do {                                                                                 \

@@ -73,7 +73,7 @@ extern "C" {
 
 const char *uavq_last_error(void) { return g_err.c_str(); }
 
-int32_t uavq_version(void) { return 100; }
+int32_t uavq_version(void) { return 101; }
 
 int uavq_qubo_build(const uavq_grid *g, uavq_qubo **out) {
     if (!g || !out) return set_error(UAVQ_EINVAL, "qubo_build: null argument");
@@ -424,6 +424,8 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     if (p->tune) pl->generic_chunk = (p->tune->variant_flags & UAVQ_VARIANT_GENERIC) ? 1 : 0;
     pl->stop_frozen = (p->flags & UAVQ_STOP_FROZEN) ? 1 : 0;
     pl->reduce_at_end = (p->flags & UAVQ_REDUCE_AT_END) ? 1 : 0;
+    pl->concurrent = (p->flags & UAVQ_CONCURRENT_CLASSES) ? 1 : 0;
+    if (p->tune) pl->concurrent |= (p->tune->variant_flags & UAVQ_CONCURRENT_CLASSES) ? 1 : 0;
     pl->persistent = (p->flags & UAVQ_PERSISTENT) ? 1 : 0;
     pl->graph = (p->flags & UAVQ_GRAPH) ? 1 : 0;
     const int32_t S = p->sweeps, R = p->replicas;

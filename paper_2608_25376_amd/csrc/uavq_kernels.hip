@@ -48,6 +48,7 @@
 #include <vector>
 
 #include "uavq_device.h"
+#include "uavq_internal.h"
 #include "uavq_factored.h"
 
 namespace uavq {
@@ -691,6 +692,26 @@ __global__ __launch_bounds__(256) void k_reduce(KArgs a) {
     }
 }
 
+// Per replica: N attempts for every sweep it ran in this launch (sweeps
+// max(start_sweep, s_begin) .. s_end-1), added to the carried count on resume.
+__global__ __launch_bounds__(256) void k_count_attempts(KArgs a) {
+    const int inst = blockIdx.x;
+    const InstDesc d = a.desc[inst];
+    const uint64_t N = (uint64_t)d.m * (uint64_t)d.m;
+    for (int r = threadIdx.x; r < d.nrep; r += blockDim.x) {
+        const int64_t g = d.rep_base + r;
+        const int s0 = max(a.start_sweep ? a.start_sweep[g] : 0, a.s_begin);
+        const uint64_t run = a.s_end > s0 ? (uint64_t)(a.s_end - s0) : 0;
+        a.attempts[g] = (a.resume ? a.attempts[g] : 0) + N * run;
+    }
+}
+
+// violations[i] += (E[i] != E_check[i]): the invariant check of anneal_checked
+__global__ void k_count_mismatch(const int64_t *E, const int64_t *E_check, uint32_t *violations, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) violations[i] += E[i] != E_check[i] ? 1u : 0u;
+}
+
 // ------------------------------------------------------------- launchers --
 static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
     // per replica: travel rows of steps 1..m plus 8 boundary rows, 64 int16 each, and 68 step counts
@@ -776,6 +797,25 @@ static int prepare(const uavq_plan *cpl) {
         pl->max_blocks[cls] = std::max(nb, 1);
         pl->lds_class[cls] = lds;
     }
+    if (pl->concurrent && !pl->dense) {
+        // one stream per class after the first (default priority), fork/join events
+        int used = 0;
+        for (int cls = 1; cls <= kMaxChunks; cls++) {
+            if (pl->class_begin[cls + 1] <= pl->class_begin[cls]) continue;
+            if (used++ == 0) continue;
+            hipStream_t s2;
+            hipEvent_t e2;
+            UAVQ_HIP(hipStreamCreateWithFlags(&s2, hipStreamNonBlocking));
+            pl->side_stream[cls] = (void *)s2;
+            UAVQ_HIP(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+            pl->join_ev[cls] = (void *)e2;
+        }
+        if (used > 1) {
+            hipEvent_t e;
+            UAVQ_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+            pl->fork_ev = (void *)e;
+        }
+    }
     pl->prepared = 1;
     return UAVQ_OK;
 }
@@ -841,11 +881,34 @@ int launch_anneal(const uavq_plan *pl, const KArgs &a0, void *stream, int64_t *c
             hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, st, (int32_t *)(a.ws + pl->queue_off), kMaxChunks + 2, 0);
             UAVQ_HIP(hipGetLastError());
         }
-        for (int cls = 1; cls <= kMaxChunks; cls++)
-            if ((rc = launch_class(pl, a, cls, st))) return rc;
+        if (pl->fork_ev) {
+            // classes at the same time: the first on st, the others on the plan's streams
+            const bool timed = pl->timing && !pl->graph;
+            if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[0], st));
+            UAVQ_HIP(hipEventRecord((hipEvent_t)pl->fork_ev, st));
+            for (int cls = 1; cls <= kMaxChunks; cls++) {
+                if (!pl->side_stream[cls]) {
+                    if ((rc = launch_class(pl, a, cls, st))) return rc;
+                    continue;
+                }
+                hipStream_t s2 = (hipStream_t)pl->side_stream[cls];
+                UAVQ_HIP(hipStreamWaitEvent(s2, (hipEvent_t)pl->fork_ev, 0));
+                if ((rc = launch_class(pl, a, cls, s2))) return rc;
+                UAVQ_HIP(hipEventRecord((hipEvent_t)pl->join_ev[cls], s2));
+                UAVQ_HIP(hipStreamWaitEvent(st, (hipEvent_t)pl->join_ev[cls], 0));
+            }
+            if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[1], st));
+        } else {
+            for (int cls = 1; cls <= kMaxChunks; cls++)
+                if ((rc = launch_class(pl, a, cls, st))) return rc;
+        }
     }
     if (!pl->reduce_at_end || a.s_end == pl->S) {
         hipLaunchKernelGGL(k_reduce, dim3(pl->n_inst), dim3(256), 0, st, a);
+        UAVQ_HIP(hipGetLastError());
+    }
+    if (a.attempts) {
+        hipLaunchKernelGGL(k_count_attempts, dim3(pl->n_inst), dim3(256), 0, st, a);
         UAVQ_HIP(hipGetLastError());
     }
     return check_E ? launch_checks(pl, a, check_E, st) : UAVQ_OK;
@@ -971,6 +1034,12 @@ int uavq_anneal_segment(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const 
     a.inst_best_sweep = out->inst_best_sweep;
     a.inst_best_state = out->inst_best_state;
     a.inst_state_off = (int64_t *)(ws + pl->inst_state_off_off);
+    a.attempts = out->attempts;
+    if (!pl->graph && pl->fork_ev) {
+        // the plan's streams and fork/join events are shared: one launch sequence at a time
+        std::lock_guard<std::mutex> lock(const_cast<uavq_plan *>(pl)->mu);
+        return launch_anneal(pl, a, stream, out->check_E);
+    }
     if (!pl->graph) return launch_anneal(pl, a, stream, out->check_E);
 
     // graph mode: replay the captured sequence while every pointer is unchanged;
@@ -980,7 +1049,8 @@ int uavq_anneal_segment(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const 
     uint64_t key = 0x12345678ull;
     const void *ptrs[] = {d_ws, stream, a.init_states, a.seeded, a.start_sweep, out->final_states, out->final_E,
                           out->best_E, out->best_sweep, out->best_states, out->accepts, out->draws, out->inst_best_E,
-                          out->inst_best_replica, out->inst_best_sweep, out->inst_best_state, out->check_E};
+                          out->inst_best_replica, out->inst_best_sweep, out->inst_best_state, out->check_E,
+                          out->attempts};
     for (const void *p : ptrs) key = mix64(key, (uint64_t)(uintptr_t)p);
     key = mix64(mix64(mix64(key, (uint64_t)s_begin), (uint64_t)s_end), (uint64_t)a.resume);
     hipStream_t st = (hipStream_t)stream;
@@ -1006,6 +1076,46 @@ int uavq_anneal_segment(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const 
     return UAVQ_OK;
 }
 
+int uavq_anneal_checked(const uavq_plan *pl, void *d_ws, size_t ws_bytes, const uavq_anneal_init *init,
+                        const uavq_anneal_out *out, int32_t refresh_every, uint32_t *d_violations,
+                        uint64_t *n_violations, void *stream) {
+    if (!pl || !out || !n_violations || refresh_every < 1)
+        return set_error(UAVQ_EINVAL, "anneal_checked: bad argument");
+    *n_violations = 0;
+    if (pl->total_rep == 0) return UAVQ_OK;
+    if (!out->check_E || !d_violations)
+        return set_error(UAVQ_EINVAL, "anneal_checked: check_E and the violation counts are required");
+    if (pl->graph) return set_error(UAVQ_EINVAL, "anneal_checked: not available in graph mode");
+    if (!d_ws || ws_bytes < pl->ws_bytes) return set_error(UAVQ_EINVAL, "anneal_checked: workspace too small");
+    if (!out->final_states || !out->final_E || !out->best_E || !out->best_sweep || !out->best_states ||
+        !out->accepts || !out->draws)
+        return set_error(UAVQ_EINVAL, "anneal_checked: a required output is NULL");
+    if (pl->total_rep > INT32_MAX) return set_error(UAVQ_ETOOBIG, "anneal_checked: too many replicas");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = pl->total_rep;
+    const unsigned blocks = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(k_fill_i32, dim3(blocks), dim3(256), 0, st, (int32_t *)d_violations, (int)n, 0);
+    UAVQ_HIP(hipGetLastError());
+    for (int32_t s = 0; s < pl->S; s += refresh_every) {
+        const int32_t e = (int32_t)std::min<int64_t>((int64_t)s + refresh_every, pl->S);
+        int rc = uavq_anneal_segment(pl, d_ws, ws_bytes, init, out, s, e, s > 0 ? 1 : 0, stream);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_count_mismatch, dim3(blocks), dim3(256), 0, st, out->final_E, out->check_E,
+                           d_violations, n);
+        UAVQ_HIP(hipGetLastError());
+    }
+    std::vector<uint32_t> v((size_t)n);
+    UAVQ_HIP(hipMemcpyAsync(v.data(), d_violations, v.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    UAVQ_HIP(hipStreamSynchronize(st));
+    uint64_t total = 0;
+    for (uint32_t x : v) total += x;
+    *n_violations = total;
+    if (total)
+        return set_error(UAVQ_EINVARIANT, "anneal_checked: %llu pieces whose kept energy differs from the recomputed one",
+                         (unsigned long long)total);
+    return UAVQ_OK;
+}
+
 int uavq_plan_set_timing(uavq_plan *pl, int32_t enable) {
     if (!pl) return set_error(UAVQ_EINVAL, "plan_set_timing: null plan");
     if (enable && !pl->ev[0]) {
@@ -1023,6 +1133,11 @@ int uavq_plan_sweep_ms(const uavq_plan *pl, float *ms) {
     if (!pl || !ms) return set_error(UAVQ_EINVAL, "plan_sweep_ms: null argument");
     if (!pl->timing || pl->graph) return set_error(UAVQ_EINVAL, "plan_sweep_ms: timing not enabled (or graph mode)");
     float total = 0.f;
+    if (pl->fork_ev) {   // concurrent classes: from the fork to the join on the caller's stream
+        UAVQ_HIP(hipEventElapsedTime(&total, (hipEvent_t)pl->ev[0], (hipEvent_t)pl->ev[1]));
+        *ms = total;
+        return UAVQ_OK;
+    }
     for (int cls = 1; cls <= kMaxChunks; cls++) {
         if (pl->class_begin[cls + 1] <= pl->class_begin[cls]) continue;
         float t = 0.f;
@@ -1040,6 +1155,13 @@ void plan_destroy_events(uavq_plan *pl) {
             pl->ev[i] = nullptr;
         }
     release_graph(pl);
+    for (int c = 0; c < kMaxChunks + 2; c++) {
+        if (pl->side_stream[c]) (void)hipStreamDestroy((hipStream_t)pl->side_stream[c]);
+        if (pl->join_ev[c]) (void)hipEventDestroy((hipEvent_t)pl->join_ev[c]);
+        pl->side_stream[c] = pl->join_ev[c] = nullptr;
+    }
+    if (pl->fork_ev) (void)hipEventDestroy((hipEvent_t)pl->fork_ev);
+    pl->fork_ev = nullptr;
 }
 
 int uavq_energy_workspace_bytes(const uavq_qubo *q, size_t *bytes) {
@@ -1178,7 +1300,9 @@ int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *ins
             t.variant_flags = var;
             uavq_anneal_params tp = *p;
             tp.sweeps = trial_sweeps;
-            tp.flags &= ~(uint32_t)(UAVQ_GRAPH | UAVQ_VARIANT_ROWMASK | UAVQ_VARIANT_NOPRODUCER);
+            // classes are timed one after another (a concurrent launch would blur their times)
+            tp.flags &= ~(uint32_t)(UAVQ_GRAPH | UAVQ_VARIANT_ROWMASK | UAVQ_VARIANT_NOPRODUCER |
+                                    UAVQ_CONCURRENT_CLASSES);
             tp.tune = &t;
             uavq_plan *pl = nullptr;
             if (uavq_plan_create(q, n_inst, inst_ids, &tp, &pl) != UAVQ_OK) continue;

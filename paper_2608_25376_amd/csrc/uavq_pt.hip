@@ -20,6 +20,7 @@
 #include <cstdint>
 
 #include "uavq_device.h"
+#include "uavq_internal.h"
 
 namespace uavq {
 

@@ -22,6 +22,7 @@
 #include <mutex>
 
 #include "uavq_device.h"
+#include "uavq_internal.h"
 
 namespace uavq {
 

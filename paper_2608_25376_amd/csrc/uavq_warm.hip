@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "uavq_device.h"
+#include "uavq_internal.h"
 
 namespace uavq {
 

@@ -26,9 +26,10 @@ VARIANT_NOPRODUCER = 0x80
 VARIANT_GENERIC = 0x400
 STOP_FROZEN = 0x100
 REDUCE_AT_END = 0x200
+CONCURRENT_CLASSES = 0x800
 CHUNK_CLASSES = 9          # sweep kernel classes by ceil(m / 64), 16-bit costs from class 7; m <= 576
 
-OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE = 0, -1, -2, -3, -4, -5
+OK, EINVAL, ENOMEM, EHIP, ETOOBIG, EINFEASIBLE, EINVARIANT = 0, -1, -2, -3, -4, -5, -6
 
 
 class UavqError(RuntimeError):
@@ -76,7 +77,7 @@ class _Init(C.Structure):
 class _Out(C.Structure):
     _fields_ = [(n, C.c_void_p) for n in (
         "final_states", "final_E", "best_E", "best_sweep", "best_states", "accepts", "draws", "inst_best_E",
-        "inst_best_replica", "inst_best_sweep", "inst_best_state", "check_E")]
+        "inst_best_replica", "inst_best_sweep", "inst_best_state", "check_E", "attempts")]
 
 
 EXPORTS = [
@@ -86,7 +87,8 @@ EXPORTS = [
     "uavq_schedule",
     "uavq_plan_create", "uavq_plan_free", "uavq_plan_info", "uavq_plan_kernel_name", "uavq_plan_layout",
     "uavq_plan_upload",
-    "uavq_anneal_batch", "uavq_anneal_segment", "uavq_plan_set_timing", "uavq_plan_sweep_ms", "uavq_autotune",
+    "uavq_anneal_batch", "uavq_anneal_segment", "uavq_anneal_checked", "uavq_plan_set_timing", "uavq_plan_sweep_ms",
+    "uavq_autotune",
     "uavq_mlp_param_count", "uavq_mlp_features", "uavq_mlp_workspace_bytes", "uavq_mlp_forward",
     "uavq_mlp_loss_grad", "uavq_mlp_adam", "uavq_quantize_marginals", "uavq_sample_seeds",
     "uavq_pt_ladder", "uavq_pt_exchange", "uavq_pt_exchange_batch",
@@ -129,6 +131,7 @@ def lib():
         L.uavq_plan_upload.argtypes = [vp, vp, C.c_size_t, vp]
         L.uavq_anneal_batch.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), vp]
         L.uavq_anneal_segment.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), C.c_int32, C.c_int32, C.c_int32, vp]
+        L.uavq_anneal_checked.argtypes = [vp, vp, C.c_size_t, P(_Init), P(_Out), C.c_int32, vp, P(C.c_uint64), vp]
         L.uavq_plan_set_timing.argtypes = [vp, C.c_int32]
         L.uavq_plan_sweep_ms.argtypes = [vp, P(C.c_float)]
         L.uavq_autotune.argtypes = [P(vp), C.c_int32, P(C.c_uint32), P(_Params), C.c_int32, C.c_char_p, P(Tune)]
@@ -309,10 +312,11 @@ class AnnealResult:
     inst_best_replica: object
     inst_best_sweep: object
     inst_best_state: object
+    attempts: object = None
 
 
 # outputs that carry a replica across a segment boundary (what a checkpoint holds)
-CHECKPOINT_FIELDS = ("final_states", "best_E", "best_sweep", "best_states", "accepts", "draws")
+CHECKPOINT_FIELDS = ("final_states", "best_E", "best_sweep", "best_states", "accepts", "draws", "attempts")
 
 
 def _sync(stream):
@@ -330,8 +334,9 @@ class Plan:
                  T1: float, seed: int = 1, dense: bool = False, waves_per_block: int = 0,
                  rowmask: bool = False, persistent: bool = False, graph: bool = False, tune: "Tune" = None,
                  no_producer: bool = False, stop_frozen: bool = False, inst_T=None, reduce_at_end: bool = False,
-                 generic_chunk: bool = False):
-        """``inst_T``: optional per-instance schedules, a sequence of (T0_i, T1_i)."""
+                 generic_chunk: bool = False, concurrent: bool = False):
+        """``inst_T``: optional per-instance schedules, a sequence of (T0_i, T1_i).  ``concurrent``:
+        the sweep kernels of different chunk classes run at the same time (UAVQ_CONCURRENT_CLASSES)."""
         self.qubos = list(qubos)
         n = len(self.qubos)
         arr = (C.c_void_p * max(n, 1))(*[q.handle.value for q in self.qubos])
@@ -343,6 +348,7 @@ class Plan:
         flags |= VARIANT_GENERIC if generic_chunk else 0
         flags |= STOP_FROZEN if stop_frozen else 0
         flags |= REDUCE_AT_END if reduce_at_end else 0
+        flags |= CONCURRENT_CLASSES if concurrent else 0
         self._tune = tune
         iT = None
         if inst_T is not None:
@@ -408,7 +414,10 @@ class Plan:
             best_sweep=z(R, torch.int32), best_states=z(W, torch.int32), accepts=z(R, torch.int64),
             draws=z(R, torch.int64), inst_best_E=z(self.n_inst, torch.int64),
             inst_best_replica=z(self.n_inst, torch.int32), inst_best_sweep=z(self.n_inst, torch.int32),
-            inst_best_state=z(inst_words, torch.int32))
+            inst_best_state=z(inst_words, torch.int32), attempts=z(R, torch.int64))
+
+    def _out_struct(self, out: AnnealResult, check_E=None) -> "_Out":
+        return _Out(*[_dptr(check_E) if f == "check_E" else _dptr(getattr(out, f, None)) for f, _ in _Out._fields_])
 
     def anneal(self, out: Optional[AnnealResult] = None, init_states=None, seeded=None, start_sweep=None,
                check_E=None, stream=None, s_begin: int = 0, s_end: Optional[int] = None,
@@ -425,7 +434,7 @@ class Plan:
                 raise ValueError("resume needs the outputs of the previous segment")
             out = self.alloc_outputs(ws.device)
         init = _Init(_dptr(init_states), _dptr(seeded), _dptr(start_sweep))
-        o = _Out(*[_dptr(getattr(out, f)) if f != "check_E" else _dptr(check_E) for f, _ in _Out._fields_])
+        o = self._out_struct(out, check_E)
         if s_begin == 0 and s_end is None and not resume:
             _check(lib().uavq_anneal_batch(self._h, _dptr(ws), self.ws_bytes, C.byref(init), C.byref(o),
                                            _stream_handle(stream)))
@@ -435,9 +444,33 @@ class Plan:
                                              1 if resume else 0, _stream_handle(stream)))
         return out
 
+    def anneal_checked(self, refresh_every: int, out: Optional[AnnealResult] = None, init_states=None,
+                       seeded=None, start_sweep=None, check_E=None, violations=None, stream=None):
+        """uavq_anneal_checked: the whole schedule in pieces of ``refresh_every`` sweeps, the
+        incrementally kept energies compared with their MFMA recomputation after each piece.
+        Returns (outputs, per-replica counts of mismatching pieces, their total); a mismatch is
+        reported through the total (the library's UAVQ_EINVARIANT), other errors raise.
+        Synchronous."""
+        import torch
+        if self.ws is None:
+            raise RuntimeError("Plan.upload() must precede anneal_checked()")
+        dev = self.ws.device
+        out = self.alloc_outputs(dev) if out is None else out
+        R = max(self.total_replicas, 1)
+        check_E = torch.zeros(R, dtype=torch.int64, device=dev) if check_E is None else check_E
+        violations = torch.zeros(R, dtype=torch.int32, device=dev) if violations is None else violations
+        init = _Init(_dptr(init_states), _dptr(seeded), _dptr(start_sweep))
+        o = self._out_struct(out, check_E)
+        n = C.c_uint64()
+        rc = lib().uavq_anneal_checked(self._h, _dptr(self.ws), self.ws_bytes, C.byref(init), C.byref(o),
+                                       int(refresh_every), _dptr(violations), C.byref(n), _stream_handle(stream))
+        if rc != EINVARIANT:
+            _check(rc)
+        return out, violations, int(n.value)
+
     def checkpoint(self, out: AnnealResult) -> dict:
         """Copy of everything a resumed segment reads (device tensors, on the stream's device)."""
-        return {f: getattr(out, f).clone() for f in CHECKPOINT_FIELDS}
+        return {f: getattr(out, f).clone() for f in CHECKPOINT_FIELDS if getattr(out, f, None) is not None}
 
     def restore(self, ckpt: dict, out: Optional[AnnealResult] = None) -> AnnealResult:
         """Write a checkpoint into output buffers (fresh ones if ``out`` is None); then resume with
@@ -445,7 +478,8 @@ class Plan:
         if out is None:
             out = self.alloc_outputs(self.ws.device)
         for f in CHECKPOINT_FIELDS:
-            getattr(out, f).copy_(ckpt[f])
+            if f in ckpt and getattr(out, f, None) is not None:
+                getattr(out, f).copy_(ckpt[f])
         return out
 
     def anneal_time_limited(self, budget_ms: float, segment_sweeps: Optional[int] = None,

@@ -12,13 +12,14 @@ def say(msg):
 
 def gpu_anneal(U, grids, R, S, T0, T1, seed=1, dense=False, wpb=0, closed=True, init_x=None, seeded=None,
                start_sweep=None, check_E=False, rowmask=False, persistent=False, graph=False, tune=None,
-               stream=None, replays=1, no_producer=False, stop_frozen=False, penalty=0, generic_chunk=False):
+               stream=None, replays=1, no_producer=False, stop_frozen=False, penalty=0, generic_chunk=False,
+               concurrent=False):
     """Anneal ``grids`` (inputs.Grid list) on cuda:0; returns (qubos, plan, numpy results)."""
     import torch
     qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly, closed=closed, dense=dense, penalty=penalty) for g in grids]
     plan = U.Plan(qs, [g.inst_id for g in grids], R, S, T0, T1, seed, dense=dense, waves_per_block=wpb,
                   rowmask=rowmask, persistent=persistent, graph=graph, tune=tune, no_producer=no_producer,
-                  stop_frozen=stop_frozen, generic_chunk=generic_chunk)
+                  stop_frozen=stop_frozen, generic_chunk=generic_chunk, concurrent=concurrent)
     plan.upload(stream=stream)
     kw = {}
     if init_x is not None:

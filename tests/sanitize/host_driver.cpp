@@ -104,7 +104,9 @@ int main() {
     CHECK(std::strlen(uavq_last_error()) > 0);
     g.rows = 30;
     g.cols = 30;
-    CHECK(uavq_qubo_build(&g, &bad) == UAVQ_ETOOBIG);
+    g.cost_scale = 10000;   // w_max = round(10^4 * 29 sqrt 2) does not fit 16 bits
+    CHECK(uavq_qubo_build(&g, &bad) == UAVQ_ETOOBIG && bad == nullptr);
+    g.cost_scale = 0;
     CHECK(uavq_qubo_build(nullptr, &bad) == UAVQ_EINVAL);
     CHECK(uavq_decode_path(qs[1], nullptr, nullptr, nullptr) == UAVQ_EINVAL);
 

@@ -314,3 +314,29 @@ def test_plan_shared_between_threads(U):
         assert not errors and len(set(results)) == 1 and len(results) == 400
     else:
         assert len(errors) == 8 and len(set(errors)) == 1
+
+
+def test_anneal_checked_argument_errors(U):
+    """anneal_checked rejects a bad piece length, missing buffers and graph-mode
+    plans before touching the device (so this runs without a GPU)."""
+    import ctypes as C
+    q = U.qubo_build(3, 3)
+    p = U.Plan([q], [0], 4, 10, 10.0, 1.0)
+    init, out = U._Init(), U._Out()
+    n = C.c_uint64(7)
+    L = U.lib()
+    assert L.uavq_anneal_checked(p._h, None, 0, C.byref(init), C.byref(out), 0, None, C.byref(n), None) == U.EINVAL
+    assert L.uavq_anneal_checked(p._h, None, 0, C.byref(init), C.byref(out), 5, None, None, None) == U.EINVAL
+    # check_E and the violation counts are required
+    assert L.uavq_anneal_checked(p._h, None, 0, C.byref(init), C.byref(out), 5, None, C.byref(n), None) == U.EINVAL
+    assert b"required" in L.uavq_last_error()
+    out.check_E = C.c_void_p(0x1000)            # never dereferenced: the workspace check fails first
+    assert L.uavq_anneal_checked(p._h, None, 0, C.byref(init), C.byref(out), 5, C.c_void_p(0x1000), C.byref(n),
+                                 None) == U.EINVAL
+    assert b"workspace" in L.uavq_last_error()
+    g = U.Plan([q], [0], 4, 10, 10.0, 1.0, graph=True)
+    assert L.uavq_anneal_checked(g._h, None, 0, C.byref(init), C.byref(out), 5, C.c_void_p(0x1000), C.byref(n),
+                                 None) == U.EINVAL
+    assert b"graph" in L.uavq_last_error()
+    assert n.value == 0
+    assert U.EINVARIANT == -6

@@ -102,6 +102,28 @@ def test_launch_shapes_identical(U):
                 assert np.array_equal(res[k], base[k]), (wpb, rowmask, persistent, k)
 
 
+def test_concurrent_classes_identical(U):
+    """UAVQ_CONCURRENT_CLASSES (the classes' kernels forked onto the plan's
+    streams and joined back) gives the serial launch's bytes: plain, persistent,
+    and captured in a graph over several replays, on a batch spanning classes
+    1 to 3."""
+    import torch
+    grids = inputs.batch(20, seed=13, side_lo=3, side_hi=14)
+    qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in grids]
+    assert len({(q.m + 63) // 64 for q in qs}) >= 3
+    say("case: concurrent classes")
+    _, _, base = gpu_anneal(U, grids, 24, 50, 150.0, 0.5, 4)
+    for persistent in (False, True):
+        _, _, res = gpu_anneal(U, grids, 24, 50, 150.0, 0.5, 4, persistent=persistent, concurrent=True)
+        for k in FIELDS:
+            assert np.array_equal(res[k], base[k]), (persistent, k)
+    stream = torch.cuda.Stream()
+    _, _, res = gpu_anneal(U, grids, 24, 50, 150.0, 0.5, 4, persistent=True, graph=True, concurrent=True,
+                           stream=stream, replays=3)
+    for k in FIELDS:
+        assert np.array_equal(res[k], base[k]), ("graph", k)
+
+
 def test_autotune_cache_roundtrip(U, tmp_path):
     grids = inputs.batch(16, seed=2)
     qs = [U.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in grids]

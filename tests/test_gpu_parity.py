@@ -402,3 +402,44 @@ def test_sixteen_bit_cost_fields(U, oracle_lib, rows, cols, dens, inst, scale, c
     reps = [0, R - 1] if m > 100 else list(range(R))
     orc = oracle_lib.anneal(o, S, T0, T1, 3, g.inst_id, reps, init_x=x0[reps], threads=2)
     compare_replicas(gi, orc, reps, f"{rows}x{cols}")
+
+
+@pytest.mark.parametrize("name,kernel", [("grid20x20", "k_sweep_factored_big<7>"),
+                                         ("grid24x24", "k_sweep_factored_big<9>")])
+def test_sixteen_bit_cost_workloads(U, oracle_lib, name, kernel):
+    """The 20x20 and 24x24 workloads in the launch the benchmark times (4096
+    replicas, 1024 workgroups), over three sweeps of a hot schedule from random
+    tours: four replicas spread over the grid against the oracle (coefficients
+    from their definition), the per-instance reduce over all 4096 replicas,
+    and the host energy of every final state against the kept one."""
+    import torch
+    w = inputs.workload(name)
+    g = w.grids[0]
+    q = U.qubo_build(g.rows, g.cols, nofly=g.nofly)
+    m, R, S, T0, T1 = q.m, w.replicas, 3, 150.0, 50.0
+    rng = np.random.default_rng(m)
+    perms = np.stack([rng.permutation(m) for _ in range(R)])      # step t visits cell perms[r, t]
+    W = q.row_words
+    packed = np.zeros((R, m, W), np.uint32)                       # one set bit per step row
+    packed[np.arange(R)[:, None], np.arange(m)[None, :], perms // 32] = np.left_shift(1, perms % 32).astype(np.uint32)
+    reps = [0, 1025, 2049, R - 1]
+    x0 = np.zeros((len(reps), m, m), np.uint8)                    # the sampled replicas, unpacked
+    x0[np.arange(len(reps))[:, None], np.arange(m)[None, :], perms[reps]] = 1
+    x0 = x0.reshape(len(reps), m * m)
+    assert np.array_equal(U.pack_states(x0, m), packed[reps].reshape(len(reps), -1))
+    say(f"case: {name} m={m} w_max={q.w_max} R={R} S={S}")
+    plan = U.Plan([q], [g.inst_id], R, S, T0, T1, w.seed)
+    assert plan.kernel_name((m + 63) // 64) == kernel
+    plan.upload()
+    packed = packed.reshape(-1)
+    out = plan.anneal(init_states=torch.from_numpy(packed.view(np.int32)).cuda(),
+                      seeded=torch.ones(R, dtype=torch.uint8, device="cuda"))
+    torch.cuda.synchronize()
+    res = {k: getattr(out, k).cpu().numpy() for k in out.__dataclass_fields__}
+    gi = split(U, [q], plan, res)[0]
+    E_host = U.energy_eval(q, res["final_states"].view(np.uint32).reshape(R, q.state_words))
+    assert np.array_equal(E_host, gi["final_E"])
+    check_reduce(oracle_lib, gi, R, f"{name} reduce")
+    o = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, dense=False)
+    orc = oracle_lib.anneal(o, S, T0, T1, w.seed, g.inst_id, reps, init_x=x0, threads=4)
+    compare_replicas(gi, orc, reps, name)

@@ -341,3 +341,33 @@ def test_anneal_boltzmann_stationary(oracle_lib):
     assert tv < 0.03, tv
     # and a wrong sign in the acceptance rule would invert the ordering
     assert emp[np.argmin(E)] > emp[np.argmax(E)]
+
+
+def test_stored_optima_of_small_fields(oracle_lib):
+    """tests/golden/optima_small_fields.json (written by oracle/paper_optima.py)
+    against geometry: from the corner of a full grid a snake path takes m unit
+    legs, so the open optimum is 10 m; a closed tour has m + 1 legs of at least
+    10, all unit when the grid has an even number of cells (a Hamiltonian cycle
+    exists), and at least one diagonal leg (14) when it is odd (the grid graph
+    is bipartite).  Batch instances: at least 10 (m + 1), the free-cell count
+    of the seeded generator, and Held-Karp recomputed where it is quick."""
+    import json
+    d = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "optima_small_fields.json")))
+    for key, v in d["paper_fields"].items():
+        dims, kind = key.split("_")
+        rows, cols = map(int, dims.split("x"))
+        m = rows * cols - 1
+        assert v["m"] == m
+        if kind == "open":
+            assert v["optimum"] == 10 * m, key
+        else:
+            assert v["optimum"] == (10 * (m + 1) if (rows * cols) % 2 == 0 else 10 * m + 14), key
+    grids = inputs.workload("batch256").grids
+    by_id = {g.inst_id: g for g in grids}
+    assert len(d["batch256"]) == sum(1 for g in grids if g.n_free <= 24)
+    for key, v in d["batch256"].items():
+        g = by_id[int(key)]
+        assert v["m"] == g.n_free and v["optimum"] >= 10 * (v["m"] + 1)
+        if v["m"] <= 15:
+            q = oracle_lib.OracleQubo(g.rows, g.cols, nofly=g.nofly, dense=False)
+            assert q.held_karp() == v["optimum"], key
