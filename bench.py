@@ -37,7 +37,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="grid12x12")
+    ap.add_argument("--workload", default="grid12x12",
+                    help="a named workload (paper_2608_25376_amd/configs/<name>.json)")
+    ap.add_argument("--config", default="", help="a workload config JSON file (instead of --workload)")
     ap.add_argument("--kernel", default="factored", choices=["factored", "dense"])
     ap.add_argument("--waves-per-block", type=int, default=0)
     ap.add_argument("--rowmask", action="store_true", help="m <= 64: rebuild travel rows from step masks")
@@ -223,7 +225,7 @@ def segment_measurements(args):
     import numpy as np
     import torch
     from paper_2608_25376_amd import inputs, uavq
-    w = inputs.workload(args.workload)
+    w = inputs.load_config(args.config) if args.config else inputs.workload(args.workload)
     cuts = [int(v) for v in args.segments.split(",")]
     assert cuts[0] == 0 and cuts[-1] == w.sweeps and cuts == sorted(cuts), "cuts must run from 0 to the sweeps"
     qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly) for g in w.grids]
@@ -350,7 +352,7 @@ def main():
     if args.segments:
         segment_measurements(args)
         return
-    w = inputs.workload(args.workload)
+    w = inputs.load_config(args.config) if args.config else inputs.workload(args.workload)
     dense = args.kernel == "dense"
     qs = [uavq.qubo_build(g.rows, g.cols, nofly=g.nofly, dense=dense) for g in w.grids]
     ids = [g.inst_id for g in w.grids]

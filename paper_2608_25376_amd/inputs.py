@@ -8,6 +8,8 @@ The paper's fields are plain M x N grids with the start cell c_{0,0}
 (Sec. II).  The workloads below add seeded no-fly cells (removed from the
 visit list) and batches of uneven sizes.
 """
+import json
+import os
 from dataclasses import dataclass, field
 from typing import List, Optional
 
@@ -68,30 +70,41 @@ class Workload:
     notes: str = ""
 
 
+CONFIG_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs")
+
+
+def fields_from_spec(spec: dict) -> List[Grid]:
+    """The grids a config's field spec names: {"kind": "grid", rows, cols, density, seed, inst}
+    or {"kind": "batch", n, seed, first_id, side | side_lo and side_hi, density_hi}."""
+    kind = spec["kind"]
+    if kind == "grid":
+        return [grid(int(spec["rows"]), int(spec["cols"]), float(spec.get("density", 0.0)),
+                     int(spec.get("seed", 1)), int(spec.get("inst", 0)))]
+    if kind == "batch":
+        return batch(int(spec["n"]), int(spec.get("seed", 1)), int(spec.get("side_lo", 4)),
+                     int(spec.get("side_hi", 10)), float(spec.get("density_hi", 0.2)),
+                     int(spec.get("first_id", 0)), spec.get("side"))
+    raise ValueError(f"unknown field kind {kind!r}")
+
+
+def load_config(path: str) -> Workload:
+    """A workload from a JSON config: name, fields (see fields_from_spec),
+    replicas, sweeps, T0, T1, seed, notes."""
+    with open(path) as f:
+        c = json.load(f)
+    return Workload(c["name"], fields_from_spec(c["fields"]), int(c["replicas"]), int(c["sweeps"]),
+                    float(c["T0"]), float(c["T1"]), int(c.get("seed", 1)), c.get("notes", ""))
+
+
+def workload_names() -> List[str]:
+    return sorted(os.path.splitext(f)[0] for f in os.listdir(CONFIG_DIR)
+                  if f.endswith(".json") and "fields" in json.load(open(os.path.join(CONFIG_DIR, f))))
+
+
 def workload(name: str) -> Workload:
-    """The named workloads (shapes and schedules of the evaluation configs)."""
-    if name == "grid3x3":
-        return Workload(name, [grid(3, 3)], 64, 1000, 100.0, 0.5, 1,
-                        "3x3, no obstacles, 8 free cells, 64 vars")
-    if name == "grid8x8_nofly0.1":
-        return Workload(name, [grid(8, 8, 0.1, 1, 0)], 1024, 2000, 200.0, 0.5, 1,
-                        "8x8, Bernoulli(0.1) no-fly cells, ~57 free cells, ~3249 vars")
-    if name == "grid12x12":
-        return Workload(name, [grid(12, 12)], 4096, 4000, 200.0, 0.5, 1,
-                        "12x12, no obstacles, 143 free cells, 20449 vars")
-    if name == "grid16x16":
-        return Workload(name, [grid(16, 16)], 4096, 1000, 200.0, 0.5, 1,
-                        "16x16, no obstacles, 255 free cells, 65025 vars (the largest factored class)")
-    if name == "grid19x19":
-        return Workload(name, [grid(19, 19)], 4096, 1000, 200.0, 0.5, 1,
-                        "19x19, no obstacles, 360 free cells, 129600 vars (the largest field with 8-bit costs)")
-    if name == "grid20x20":
-        return Workload(name, [grid(20, 20)], 4096, 1000, 200.0, 0.5, 1,
-                        "20x20, no obstacles, 399 free cells, 159201 vars, costs up to 269 (16-bit)")
-    if name == "grid24x24":
-        return Workload(name, [grid(24, 24)], 4096, 1000, 200.0, 0.5, 1,
-                        "24x24, no obstacles, 575 free cells, 330625 vars, costs up to 325 (16-bit)")
-    if name == "batch256":
-        return Workload(name, batch(256, 1), 256, 2000, 200.0, 0.5, 1,
-                        "256 instances, side U{4..10}, density U[0,0.2]")
-    raise KeyError(name)
+    """The named workloads (shapes and schedules of the evaluation configs),
+    one JSON file each under configs/."""
+    path = os.path.join(CONFIG_DIR, name + ".json")
+    if not os.path.exists(path):
+        raise KeyError(name)
+    return load_config(path)

@@ -385,21 +385,26 @@ def save_labels(path, data):
              labels=np.concatenate([d[1] for d in data]).astype(np.int32))
 
 
+CONFIG = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs", "warmstart_grid10x10.json")
+
+
 def main():
+    with open(CONFIG) as f:
+        cfg = json.load(f)    # the study's shape: field counts, replicas, sweeps, ladder
     ap = argparse.ArgumentParser()
-    ap.add_argument("--train-n", type=int, default=2000)
-    ap.add_argument("--heldout-n", type=int, default=200)
+    ap.add_argument("--train-n", type=int, default=cfg["train"]["n"])
+    ap.add_argument("--heldout-n", type=int, default=cfg["heldout"]["n"])
     ap.add_argument("--schedule", default="auto",
                     help="'auto' (chosen on training instances among SCHEDULE_CANDIDATES) or T0,T1")
     ap.add_argument("--choose-n", type=int, default=100, help="training instances that choose the schedule")
     ap.add_argument("--choose-sweeps", type=int, default=100)
-    ap.add_argument("--label-replicas", type=int, default=4096)
-    ap.add_argument("--label-sweeps", type=int, default=400)
-    ap.add_argument("--replicas", type=int, default=256)
+    ap.add_argument("--label-replicas", type=int, default=cfg["label_replicas"])
+    ap.add_argument("--label-sweeps", type=int, default=cfg["label_sweeps"])
+    ap.add_argument("--replicas", type=int, default=cfg["replicas"])
     ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--lr", type=float, default=3e-3)
     ap.add_argument("--batch", type=int, default=32)
-    ap.add_argument("--ladder", default="10,20,50,100,200,400,800")
+    ap.add_argument("--ladder", default=",".join(str(v) for v in cfg["ladder"]))
     ap.add_argument("--ref-sweeps", type=int, default=3200)
     ap.add_argument("--T-warm", type=float, default=0.0, help="0 = choose on training instances")
     ap.add_argument("--no-single", action="store_true")
