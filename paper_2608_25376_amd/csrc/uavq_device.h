@@ -104,12 +104,6 @@ static __device__ __attribute__((noinline)) uint2 draw_cuts(uint32_t cbase, uint
     return make_uint2((uint32_t)c0 | ((uint32_t)c1 << 16), (uint32_t)c2 | ((uint32_t)c3 << 16));
 }
 
-// The Philox words of one lane's block of four steps, out of line (see above).
-static __device__ __attribute__((noinline)) uint4 draw_words(uint32_t cbase, uint32_t s, uint32_t r, uint32_t inst,
-                                                             uint32_t seed) {
-    return philox(make_uint4(cbase, s, r, inst), seed, 0u);
-}
-
 // Work-item loop: one item per block, or (persistent mode) items pulled in
 // order from a counter until the class is exhausted.
 __device__ __forceinline__ int next_item(const KArgs &a, int iter) {

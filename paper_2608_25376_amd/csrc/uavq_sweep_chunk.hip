@@ -328,8 +328,9 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                     any |= need[i];
                                 }
                                 if (!ballot64(any)) continue;
-                                const uint4 u4 = draw_words((uint32_t)(64 * j + L) + 65536u * (uint32_t)tb,
-                                                            (uint32_t)s, (uint32_t)r, d.inst_id, a.seed);
+                                const uint4 u4 = philox(make_uint4((uint32_t)(64 * j + L) + 65536u * (uint32_t)tb,
+                                                                   (uint32_t)s, (uint32_t)r, d.inst_id),
+                                                        a.seed, 0u);
                                 const uint32_t uw[4] = {u4.x, u4.y, u4.z, u4.w};
                                 // unconditional reads (index 0 where no draw happens) issue together
                                 uint32_t th[4];
