@@ -211,7 +211,10 @@ def mlp_measurement():
 _CSRC = "paper_2608_25376_amd/csrc/"
 _COMMON = [_CSRC + "uavq_device.h", _CSRC + "uavq_kargs.h"]
 KERNEL_SOURCES = {
-    "k_sweep_chunk": [_CSRC + "uavq_sweep_chunk.hip"] + _COMMON,
+    "k_sweep_chunk": [_CSRC + "uavq_sweep_chunk.hip", _CSRC + "uavq_chunk.h"] + _COMMON,
+    "k_sweep_chunk<5>": [_CSRC + "uavq_sweep_chunk_wide.hip", _CSRC + "uavq_chunk.h"] + _COMMON,
+    "k_sweep_chunk<6>": [_CSRC + "uavq_sweep_chunk_wide.hip", _CSRC + "uavq_chunk.h"] + _COMMON,
+    "k_sweep_chunk_big": [_CSRC + "uavq_sweep_chunk_big.hip", _CSRC + "uavq_chunk.h"] + _COMMON,
     "k_sweep_factored_big": [_CSRC + "uavq_sweep_big.hip", _CSRC + "uavq_factored.h"] + _COMMON,
     "k_sweep_dense": [_CSRC + "uavq_refresh.hip", _CSRC + "uavq_internal.h"] + _COMMON,
     "k_sweep": [_CSRC + "uavq_kernels.hip", _CSRC + "uavq_factored.h", _CSRC + "uavq_internal.h"] + _COMMON,

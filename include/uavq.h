@@ -170,7 +170,7 @@ int uavq_schedule(double T0, double T1, int32_t S, int32_t *Dmax, uint32_t *thr)
                                       along the schedule: plan_create checks, EINVAL otherwise), so
                                       every output is the same; the launch ends when all are frozen.
                                       Not for throughput measurements: frozen sweeps are not evaluated. */
-#define UAVQ_VARIANT_GENERIC 0x400u /* 64 < m <= 192: the generic chunked walk (every step walked) instead
+#define UAVQ_VARIANT_GENERIC 0x400u /* 64 < m <= 384: the generic chunked walk (every step walked) instead
                                       of the kernel that first tests blocks of four steps whose steps
                                       each hold one cell (a schedule choice; same results) */
 #define UAVQ_CONCURRENT_CLASSES 0x800u /* the sweep kernels of different chunk classes run at the same

@@ -7,9 +7,10 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libuavq.so")
-SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_sweep_chunk.hip", "uavq_sweep_big.hip", "uavq_refresh.hip",
+SOURCES = ["uavq_host.cpp", "uavq_kernels.hip", "uavq_sweep_chunk.hip", "uavq_sweep_chunk_wide.hip", "uavq_sweep_chunk_big.hip",
+           "uavq_sweep_big.hip", "uavq_refresh.hip",
            "uavq_warm.hip", "uavq_pt.hip"]
-HEADERS = ["uavq_internal.h", "uavq_kargs.h", "uavq_device.h", "uavq_factored.h", os.path.join("..", "..", "include", "uavq.h")]
+HEADERS = ["uavq_internal.h", "uavq_kargs.h", "uavq_device.h", "uavq_factored.h", "uavq_chunk.h", os.path.join("..", "..", "include", "uavq.h")]
 ARCH = os.environ.get("UAVQ_OFFLOAD_ARCH", "gfx950")
 
 
@@ -47,6 +48,8 @@ def build(force: bool = True, verbose: bool = False) -> str:
     # kernels of the file compile to the same code with or without this.
     per_file = {"uavq_kernels.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
                 "uavq_sweep_chunk.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
+                "uavq_sweep_chunk_wide.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
+                "uavq_sweep_chunk_big.hip": ["-mllvm", "-pragma-unroll-threshold=200000"],
                 "uavq_sweep_big.hip": ["-mllvm", "-pragma-unroll-threshold=200000"]}
     objs, cmds = [], []
     for s in SOURCES:

@@ -71,8 +71,12 @@ extern "C" void plan_destroy_events(uavq_plan *pl);   // also releases a cached 
 
 // Kernel launchers (uavq_kernels.hip).
 namespace uavq {
-// the block-tested chunked sweep for nj = 2, 3 chunks (uavq_sweep_chunk.hip); NULL otherwise
+// the block-tested chunked sweep for nj = 2, 3, 4 chunks (uavq_sweep_chunk.hip); NULL otherwise
 const void *chunk_sweep_kernel(int nj, bool stop);
+// ... for nj = 5, 6 (uavq_sweep_chunk_wide.hip); NULL otherwise
+const void *chunk_sweep_wide_kernel(int nj, bool stop);
+// ... for nj = 7, 8, 9 with 16-bit costs in global memory (uavq_sweep_chunk_big.hip); NULL otherwise
+const void *chunk_sweep_big_kernel(int nj, bool stop);
 // the 16-bit-cost sweep of classes 7..9 (uavq_sweep_big.hip); NULL otherwise
 const void *big_sweep_kernel(int nj, bool stop);
 int launch_anneal(const uavq_plan *plan, const KArgs &a, void *stream, int64_t *check_E);

@@ -751,7 +751,9 @@ static const void *class_kernel_t(const uavq_plan *pl, int cls) {
     if (cls == 1 && use_ylds(pl))
         return pl->ylds_w1 ? (const void *)k_sweep_ylds_w1<STOP> : (const void *)k_sweep_ylds<STOP>;
     if (cls == 1) return (const void *)k_sweep_factored<1, STOP>;
-    if ((cls == 2 || cls == 3) && !pl->generic_chunk) return chunk_sweep_kernel(cls, STOP);
+    if (cls >= 2 && cls <= 4 && !pl->generic_chunk) return chunk_sweep_kernel(cls, STOP);
+    if ((cls == 5 || cls == 6) && !pl->generic_chunk) return chunk_sweep_wide_kernel(cls, STOP);
+    if (cls >= 7 && !pl->generic_chunk) return chunk_sweep_big_kernel(cls, STOP);
     if (cls == 2) return (const void *)k_sweep_factored<2, STOP>;
     if (cls == 3) return (const void *)k_sweep_factored<3, STOP>;
     if (cls == 4) return (const void *)k_sweep_factored4<STOP>;
@@ -970,6 +972,11 @@ const char *uavq_plan_kernel_name(const uavq_plan *pl, int32_t cls) {
     if (cls == 1 && uavq::use_ylds(pl)) return pl->ylds_w1 ? "k_sweep_ylds_w1" : "k_sweep_ylds";
     if (cls == 2 && !pl->generic_chunk) return "k_sweep_chunk<2>";
     if (cls == 3 && !pl->generic_chunk) return "k_sweep_chunk<3>";
+    if (cls == 4 && !pl->generic_chunk) return "k_sweep_chunk<4>";
+    if (cls == 5 && !pl->generic_chunk) return "k_sweep_chunk<5>";
+    if (cls == 6 && !pl->generic_chunk) return "k_sweep_chunk<6>";
+    if (cls == 7 && !pl->generic_chunk) return "k_sweep_chunk_big<7>";
+    if (cls >= 8 && !pl->generic_chunk) return "k_sweep_chunk_big<9>";
     static const char *const names[] = {"", "k_sweep_factored<1>", "k_sweep_factored<2>", "k_sweep_factored<3>",
                                         "k_sweep_factored4", "k_sweep_factored_wide<5>", "k_sweep_factored_wide<6>",
                                         "k_sweep_factored_big<7>", "k_sweep_factored_big<9>",

@@ -30,6 +30,8 @@ def U():
     ("ylds", [(6, 6, 0.1, 2)], 64, 300, {"wpb": 8}, 1, "k_sweep_ylds"),
     ("chunk2", [(9, 9, 0.1, 3)], 32, 300, {}, 2, "k_sweep_chunk<2>"),
     ("chunk3", [(12, 12, 0.0, 4)], 16, 200, {}, 3, "k_sweep_chunk<3>"),
+    ("chunk4", [(15, 15, 0.05, 8)], 8, 200, {}, 4, "k_sweep_chunk<4>"),
+    ("chunk5", [(18, 18, 0.1, 9)], 4, 150, {}, 5, "k_sweep_chunk<5>"),
     ("factored2", [(9, 9, 0.1, 3)], 32, 300, {"generic_chunk": True}, 2, "k_sweep_factored<2>"),
     ("factored3", [(12, 12, 0.0, 4)], 16, 200, {"generic_chunk": True}, 3, "k_sweep_factored<3>"),
     ("persistent_batch", [(4, 4, 0.0, 5), (10, 10, 0.1, 6), (5, 6, 0.2, 7)], 24, 300, {"persistent": True}, 2,
