@@ -175,12 +175,11 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     if (w < W) bs[(t - 1) * W + w] = rm[j][w];
         }
     }
-    int dep[NJ];   // start-cell costs of this lane's cells (the fixed rows 0 and m+1)
-#pragma unroll
-    for (int j = 0; j < NJ; j++) {
+    // start-cell costs of this lane's cells (the fixed rows 0 and m+1), read where needed
+    auto dep = [&](int j) -> int {
         const int c = 64 * j + L;
-        dep[j] = c < m ? sdep[c] : 0;
-    }
+        return c < m ? (int)sdep[c] : 0;
+    };
     // occupation counts and initial energy (grouped pair sums of the QUBO)
     int Cc[NJ];
 #pragma unroll
@@ -190,7 +189,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
         int64_t lane_e = 0, rowterm = 0;
         int Yp[NJ];
 #pragma unroll
-        for (int j = 0; j < NJ; j++) Yp[j] = dep[j];
+        for (int j = 0; j < NJ; j++) Yp[j] = dep(j);
 #pragma unroll
         for (int jt = 0; jt < NJ; jt++)
             for (int lt = 0; lt < 64; lt++) {
@@ -209,7 +208,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     const int x = lane_in_mask(mk[2 * j], mk[2 * j + 1]) ? 1 : 0;
                     Cc[j] += x;
                     lane_e += x * Yp[j];
-                    if (t == m && d.closed && 64 * j + L < m) lane_e += x * dep[j];
+                    if (t == m && d.closed && 64 * j + L < m) lane_e += x * dep(j);
                     Yt[j] = 0;
                 }
 #pragma unroll
@@ -257,7 +256,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
     auto yrow = [&](int t, uint32_t sv, const uint32_t *mkq, int (&Y)[NJ]) {
         if (t > m) {
 #pragma unroll
-            for (int j = 0; j < NJ; j++) Y[j] = (t == m + 1 && d.closed) ? dep[j] : 0;
+            for (int j = 0; j < NJ; j++) Y[j] = (t == m + 1 && d.closed) ? dep(j) : 0;
             return;
         }
         const uint32_t R = sv & 0xffffu;
@@ -290,7 +289,8 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
     // (a field of a class taken for its costs alone may leave the last chunk empty: no packing then)
     const int nl = max(m - 64 * (NJ - 1), 1);
     const int kp = m > 64 * (NJ - 1) ? 64 / nl : 1;
-    const int pk_b = L / nl, pk_c = L - pk_b * nl;
+    // L / nl as (L ceil(2^16 / nl)) >> 16: exact for L < 64 (the error stays below 64 / 2^16 < 1 - (nl - 1) / nl)
+    const uint32_t nl_inv = (65536u + (uint32_t)nl - 1u) / (uint32_t)nl;
 
     for (int s = s_first; s < a.s_end; s++) {
         // next table row: loads issued now, stored to LDS after this sweep
@@ -313,7 +313,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
             // window of travel rows Y_{t0-1} .. Y_{t0+4} of the current block
             int Yw[6][NJ];
 #pragma unroll
-            for (int j = 0; j < NJ; j++) Yw[0][j] = dep[j];
+            for (int j = 0; j < NJ; j++) Yw[0][j] = dep(j);
 #pragma unroll
             for (int k = 1; k <= 5; k++) {
                 uint32_t mk[2 * NJ];
@@ -332,6 +332,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                 if (tb >= pk_g0 + kp) {
                     // blocks tb .. tb + kp - 1 of the last chunk, one per group of nl lanes
                     pk_g0 = tb;
+                    const int pk_b = (int)(__umul24((uint32_t)L, nl_inv) >> 16), pk_c = L - pk_b * nl;
                     const uint4 u4 = philox(make_uint4((uint32_t)(64 * (NJ - 1) + pk_c) + 65536u * (uint32_t)(tb + pk_b),
                                                        (uint32_t)s, (uint32_t)r, d.inst_id),
                                             a.seed, 0u);

@@ -392,7 +392,8 @@ class Plan:
         _check(lib().uavq_plan_set_timing(self._h, 1 if enable else 0))
 
     def kernel_name(self, cls=1):
-        """Sweep kernel launched for chunk class cls (1: m <= 64, 2: <= 128, 3: <= 192, 4: <= 256); '' if unused."""
+        """Sweep kernel launched for chunk class cls (1: m <= 64, 2: <= 128, ..., 9: <= 576; fields whose costs
+        exceed 255 run in class 7 or above); '' if the class is empty."""
         v = lib().uavq_plan_kernel_name(self._h, int(cls))
         if v is None:
             raise UavqError(-1, lib().uavq_last_error().decode())
