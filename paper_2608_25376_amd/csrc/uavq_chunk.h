@@ -175,10 +175,23 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     if (w < W) bs[(t - 1) * W + w] = rm[j][w];
         }
     }
-    // start-cell costs of this lane's cells (the fixed rows 0 and m+1), read where needed
-    auto dep = [&](int j) -> int {
+    // start-cell costs of this lane's cells (the fixed rows 0 and m+1): kept in
+    // registers from four chunks on; up to three chunks, where the 1024-thread
+    // bound leaves 128 registers, read where needed (fewer spills)
+    constexpr bool kDepRegs = NJ >= 4;
+    int depr[kDepRegs ? NJ : 1];
+#pragma unroll
+    for (int j = 0; j < (kDepRegs ? NJ : 1); j++) {
         const int c = 64 * j + L;
-        return c < m ? (int)sdep[c] : 0;
+        depr[j] = kDepRegs && c < m ? (int)sdep[c] : 0;
+    }
+    auto dep = [&](int j) -> int {
+        if constexpr (kDepRegs) {
+            return depr[j];
+        } else {
+            const int c = 64 * j + L;
+            return c < m ? (int)sdep[c] : 0;
+        }
     };
     // occupation counts and initial energy (grouped pair sums of the QUBO)
     int Cc[NJ];

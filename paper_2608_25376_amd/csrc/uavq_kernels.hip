@@ -31,11 +31,16 @@
 // block-start state, which finishes most blocks at low temperature without
 // the walk.  When one replica runs per SIMD (k_sweep_ylds_pc) a second wave
 // per replica computes the next sweep's random words and acceptance cuts.
-// m <= 384 (k_sweep_factored*): lane L holds the cell masks of steps
-// L + 1 + 64 j (bits = cells) and the occupation count of cells L + 64 j, and
-// travel rows are rebuilt from the neighbouring steps' masks.
-// The cost matrix D, the start-cell costs and one row of the acceptance table
-// live in LDS and are shared by the block's replicas.
+// 64 < m <= 576 (the generic chunked walk k_sweep_factored*, here and in
+// uavq_factored.h): lane L holds the cell masks of steps L + 1 + 64 j (bits =
+// cells) and the occupation count of cells L + 64 j, and travel rows are
+// rebuilt from the neighbouring steps' masks.  The block-tested sweep of the
+// same classes (k_sweep_chunk*, uavq_chunk.h) is launched by default; the
+// generic walk stays as the variant it is checked against.
+// One row of the acceptance table lives in LDS, shared by the block's
+// replicas, and so do the cost matrix D and the start-cell costs as bytes
+// (m <= 384 and costs below 256; otherwise they are read as 16-bit entries
+// from global memory).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -124,7 +129,7 @@ __global__ __launch_bounds__(64 * kWideMaxWaves) __attribute__((amdgpu_waves_per
 
 // Classes 5 and 6 (m <= 384, fields up to 19x19 with 8-bit costs): the same
 // chunked walk; the lane's step masks (up to 72 words) leave room for one wave
-// per SIMD only, and part of the per-lane arrays lives in scratch memory.
+// per SIMD only (fully unrolled per-chunk loops keep them in registers).
 template <int NJ, bool STOP>
 __global__ __launch_bounds__(64 * kWideMaxWaves) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_sweep_factored_wide(
     KArgs a) {
