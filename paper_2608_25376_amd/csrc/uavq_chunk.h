@@ -1,5 +1,7 @@
-// Chunked Metropolis sweep for 64 < m <= 256 (two to four 64-cell chunks
-// per lane; the 12x12 field has m = 143), gfx950.
+// Block-tested chunked Metropolis sweep for 64 < m <= 576 (two to nine
+// 64-cell chunks per lane; the 12x12 field has m = 143), gfx950.  Built by
+// uavq_sweep_chunk.hip (two to four chunks), uavq_sweep_chunk_wide.hip (five
+// and six) and uavq_sweep_chunk_big.hip (seven to nine, 16-bit costs).
 //
 // Same trajectory as the in-order sequential sweep, bit for bit (model and
 // walk: see uavq_kernels.hip).  One wavefront anneals one replica; lane L
@@ -9,7 +11,7 @@
 //  * Step summaries.  Lane L keeps, for the steps 64 j + L + 1, the number of
 //    set cells R_t and the lowest set cell p_t.  When R_t = 1 (the state is a
 //    tour there) the travel row Y_t = D^T x_t is the cost row D[p_t][.]: one
-//    LDS byte read per chunk, no scan of the step's mask.
+//    read per chunk, no scan of the step's mask.
 //  * Quiet blocks.  Steps are taken in blocks of four (the four steps that
 //    share one Philox call per cell).  If every step of a block has R_t = 1,
 //    the block is first evaluated against the state at its start: with no

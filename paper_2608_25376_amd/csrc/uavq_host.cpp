@@ -371,9 +371,13 @@ static int inst_class(const uavq_qubo *q, bool dense) {
     return q->wmax > 255 ? std::max(c, kByteChunks + 1) : c;
 }
 
+// Replicas per workgroup by chunk class: eight for three chunks (one
+// table-row copy per sweep serves eight replicas; measured on the 12x12 field:
+// 371 ms against 377 with four and 374 with sixteen), four otherwise (two
+// chunks with eight: the 256-field batch took 774 ms against 738, its last
+// workgroups running longer alone).
 static int default_waves_per_block(int chunks) {
-    (void)chunks;
-    return 4;
+    return chunks == 3 ? 8 : 4;
 }
 
 int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *inst_ids,
