@@ -54,6 +54,14 @@ __device__ __forceinline__ bool lane_in_mask(uint32_t lo, uint32_t hi) {
     return __builtin_amdgcn_inverse_ballot_w64(((uint64_t)hi << 32) | (uint64_t)lo);
 }
 
+// c + a b with a, b in 24 bits, as one full-rate v_mad_i32_i24 (written out: for a byte a, the
+// compiler otherwise picks the 64-bit v_mad_u64_u32 for the product and the add)
+__device__ __forceinline__ int mad_i24(int a, int b, int c) {
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "s"(b), "v"(c));
+    return r;
+}
+
 __device__ __forceinline__ uint32_t rl(uint32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
 // value v into the lane `lane` of old (one compare shared by the caller's selects)
 __device__ __forceinline__ uint32_t wl(uint32_t v, bool mine, uint32_t old) { return mine ? v : old; }
@@ -339,7 +347,23 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                 yrow(k, sv, mk, Yw[k]);
             }
             bool spec = true;
+            // one-cell steps: bit L of tmk[j] is set iff step 64 j + L + 1 holds exactly one cell (steps past m
+            // hold none), so that the block tests take a shift and a compare; rebuilt after each walked block
+            uint64_t tmk[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; j++) tmk[j] = ballot64((si[j] & 0xffffu) == 1u);
             bool eager = false;   // the last walked block drew in every chunk (hot): draw this block's up front
+            // The state is a permutation (every step one cell, every cell one step) and dcut <= 2P - 2 w_max:
+            // a set site's dE = 4P - (Y_{t-1} + Y_{t+1} + 2P) >= 2P - 2 w_max >= dcut is never below the cut, and
+            // its v = Y_{t-1} + Y_{t+1} + 2P >= dcut never passes for a clear site's.  Quiet blocks then need only
+            // min v >= dcut.  Cleared for the rest of the sweep by an accepted flip.
+            bool perm = false;
+            if (dcut <= twoP - 2 * d.wmax) {
+                bool ok = true;
+#pragma unroll
+                for (int j = 0; j < NJ; j++) ok &= 64 * j + L >= m || (KC[j] == twoP && (si[j] & 0xffffu) == 1u);
+                perm = !ballot64(!ok);
+            }
             int pk_g0 = INT_MIN / 2;   // first block of the packed last-chunk cuts held in pk0, pk1
             uint32_t pk0 = 0u, pk1 = 0u;
             // exact cuts of block tb of the last chunk (lanes < nl), from the packed draw of its group
@@ -374,15 +398,25 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     // ---- quiet-block test (every step of the block holds one cell: the
                     // low halves of the four summaries are all 1)
                     bool done = false;
-                    const uint32_t s_or = sx[0] | sx[1] | sx[2] | sx[3], s_and = sx[0] & sx[1] & sx[2] & sx[3];
-                    const bool tours = spec && t0 + 3 <= m && (s_or & 0xfffe) == 0 && (s_and & 1);
+                    const bool tours = spec && ((tmk[jt] >> q0) & 0xfull) == 0xfull;
                     // R_t = 1: dE = v for x = 0 and 4P - v for x = 1, v = Y_{t-1} + Y_{t+1} + 2P C_c;
                     // x = 1 exactly at the lane whose cell the summary names
                     auto dEq = [&](int i, int j) {
                         const int v = Yw[i][j] + Yw[i + 2][j] + KC[j];
                         return ckey[j] == sx[i] ? fourP - v : v;
                     };
-                    if (tours) {
+                    bool quick = false;
+                    if (tours && perm) {
+                        int mv = INT_MAX;
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+#pragma unroll
+                            for (int j = 0; j < NJ; j++) mv = min(mv, Yw[i][j] + Yw[i + 2][j] + KC[j]);
+                        quick = !ballot64(mv < dcut);
+                    }
+                    if (quick) {
+                        done = true;
+                    } else if (tours) {
                         int mn = INT_MAX;
 #pragma unroll
                         for (int i = 0; i < 4; i++)
@@ -479,7 +513,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             // a step with no site below the cut is finished: no accept, no draw
                             if (!ballot64(mnv < dcut)) continue;
                             const int ti = i;
-                            int k = 0, psn = 0;   // psn: 0 while the pending cost row adds, -1 when it subtracts
+                            int k = 0, sg = 1;   // sg: +1 while the pending cost row adds, -1 when it subtracts
                             uint64_t accd[NJ];
                             int dY[NJ], pd[NJ];
 #pragma unroll
@@ -496,11 +530,11 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                 const uint64_t rowj = ((uint64_t)mc[2 * j + 1] << 32) | (uint64_t)mc[2 * j];
                                 const bool clears = (rowj >> Ls) & 1ull;
 #pragma unroll
-                                for (int jj = 0; jj < NJ; jj++) dY[jj] += (pd[jj] ^ psn) - psn;
+                                for (int jj = 0; jj < NJ; jj++) dY[jj] = mad_i24(pd[jj], sg, dY[jj]);
                                 const auto drow = sD + (64 * j + Ls) * m;
 #pragma unroll
                                 for (int jj = 0; jj < NJ; jj++) pd[jj] = drow[64 * jj + L];
-                                psn = clears ? -1 : 0;
+                                sg = clears ? -1 : 1;
                                 k += clears ? -1 : 1;
                                 openm &= ~1ull << Ls;   // the walk resumes after Ls
                             };
@@ -555,7 +589,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                 }
                             } else {
 #pragma unroll
-                                for (int jj = 0; jj < NJ; jj++) dY[jj] += (pd[jj] ^ psn) - psn;
+                                for (int jj = 0; jj < NJ; jj++) dY[jj] = mad_i24(pd[jj], sg, dY[jj]);
                                 // visit-time dE of every site (dE0 plus the slope per net flip
                                 // before it in site order), then draws, energy, counts and masks
                                 int nab = 0, nrb = 0;   // adds / removes in earlier chunks
@@ -604,7 +638,11 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             }
                         }
                         spec = nacc_s == acc_before;
+                        perm = perm && spec;
                         eager = drawn == (1u << NJ) - 1u && !spec;
+                        // the masks again from the summaries (not held over the walk, whose registers are scarce)
+#pragma unroll
+                        for (int j = 0; j < NJ; j++) tmk[j] = ballot64((si[j] & 0xffffu) == 1u);
                     }
                     // shift the window by four steps; the new rows (steps t0+5 .. t0+8:
                     // lanes q0+5.. of chunk jt, or of chunk jt+1 past lane 63) were not
@@ -626,8 +664,14 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                 sv[k] = q < 64 ? rl(si[jt], q) : rl(si[jt + 1 < NJ ? jt + 1 : jt], q - 64);
                             }
                         }
-                        const uint32_t l_or = sv[0] | sv[1] | sv[2] | sv[3], l_and = sv[0] & sv[1] & sv[2] & sv[3];
-                        if (t0 + 8 <= m && (l_or & 0xfffe) == 0 && (l_and & 1)) {
+                        // steps t0+5 .. t0+8 are lanes q0+5 .. q0+8 of chunk jt, past 63 of chunk jt + 1
+                        const int sh = q0 + 5;   // 5 .. 65
+                        uint64_t nb = sh < 64 ? tmk[jt] >> sh : 0ull;
+                        if (jt + 1 < NJ && sh > 60) {
+                            const uint64_t hi = tmk[jt + 1 < NJ ? jt + 1 : jt];
+                            nb = sh < 64 ? nb | (hi << (64 - sh)) : hi >> (sh - 64);
+                        }
+                        if ((nb & 0xfull) == 0xfull) {
                             // four one-cell steps: their cost rows
 #pragma unroll
                             for (int k = 0; k < 4; k++) {

@@ -561,7 +561,7 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
         d.inst_id = inst_ids[i];
         d.chunks = inst_class(qi, dense);
         d.wide = qi->wmax > 255 ? 1 : 0;
-        d.pad_ = 0;
+        d.wmax = qi->wmax;
         const int32_t sj = sched_of[i];
         d.sched_row = sched_row[sj];
         d.sched_step = sched_rows[sj] > 1 ? 1 : 0;

@@ -37,7 +37,7 @@ struct InstDesc {
     int32_t sched_row, sched_step;
     float tl2_a, tl2_b; // T_s ln 2 ~= exp2(tl2_a + tl2_b s): starting guess for acceptance cuts
     int32_t wide;       // a cost exceeds 255 (no byte copy of D for the MFMA energy check)
-    int32_t pad_;
+    int32_t wmax;       // largest travel cost, start cell included
 };
 
 // One workgroup's share: replicas rep0 .. rep0+nrep-1 of instance inst.
