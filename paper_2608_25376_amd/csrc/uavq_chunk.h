@@ -387,7 +387,34 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
             };
 #pragma unroll
             for (int jt = 0; jt < NJ; jt++) {
-                for (int q0 = 0; q0 < 64; q0 += 4) {
+                int q0 = 0;
+                if (perm) {
+                    // The common case once the state is a permutation: blocks of one-cell steps whose next four
+                    // steps (same chunk) hold one cell each too, quiet by the min test.  The window moves on and
+                    // nothing else changes (what the general loop below does for them, in fewer steps); the
+                    // first other block goes to the general loop.
+                    while (q0 <= 52 && ((tmk[jt] >> q0) & 0x1efull) == 0x1efull) {
+                        int mv = INT_MAX;
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+#pragma unroll
+                            for (int j = 0; j < NJ; j++) mv = min(mv, Yw[i][j] + Yw[i + 2][j] + KC[j]);
+                        if (ballot64(mv < dcut)) break;
+#pragma unroll
+                        for (int j = 0; j < NJ; j++) {
+                            Yw[0][j] = Yw[4][j];
+                            Yw[1][j] = Yw[5][j];
+                        }
+#pragma unroll
+                        for (int k = 0; k < 4; k++) {
+                            const auto row = sD + Summary<NJ>::row(rl(si[jt], q0 + 5 + k), m);
+#pragma unroll
+                            for (int j = 0; j < NJ; j++) Yw[2 + k][j] = row[64 * j + L];
+                        }
+                        q0 += 4;
+                    }
+                }
+                for (; q0 < 64; q0 += 4) {
                     const int t0 = 64 * jt + q0 + 1;
                     if (t0 > m) break;
                     const int tb = (t0 - 1) >> 2;
