@@ -49,6 +49,8 @@ constexpr int kBigK = 1 << 29;   // K of padding lanes: dE stays far above every
 // 32-bit (a generic pointer makes the compiler form 64-bit addresses)
 typedef __attribute__((address_space(3))) uint8_t lds_u8;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
 
 __device__ __forceinline__ bool lane_in_mask(uint32_t lo, uint32_t hi) {
     return __builtin_amdgcn_inverse_ballot_w64(((uint64_t)hi << 32) | (uint64_t)lo);
@@ -130,6 +132,10 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
         sD = lsm + 4 * Ts;
         sdep = sD + (int)al16((size_t)m * m);
     }
+    // the per-wave words of the last chunk's packed draws (two and three chunks, costs in LDS): 64 lanes x uint4
+    constexpr bool kPW = NJ <= 3 && !DG;
+    lds_u32 *const pwd = (lds_u32 *)(lsm + 4 * Ts + (DG ? 16 : (int)(al16((size_t)m * m) + al16((size_t)m) + 64)) +
+                                     1024 * wave);
     __shared__ int s_first_sh;
     __shared__ int s_live[2];
 
@@ -365,6 +371,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                 perm = !ballot64(!ok);
             }
             int pk_g0 = INT_MIN / 2;   // first block of the packed last-chunk cuts held in pk0, pk1
+            int pw_g0 = INT_MIN / 2;   // first block of the packed last-chunk words held in pwd
             uint32_t pk0 = 0u, pk1 = 0u;
             // exact cuts of block tb of the last chunk (lanes < nl), from the packed draw of its group
             auto packed_cuts = [&](int tb) {
@@ -467,9 +474,28 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                     any |= need[i];
                                 }
                                 if (!ballot64(any)) continue;
-                                const uint4 u4 = philox(make_uint4((uint32_t)(64 * j + L) + 65536u * (uint32_t)tb,
-                                                                   (uint32_t)s, (uint32_t)r, d.inst_id),
-                                                        a.seed, 0u);
+                                uint4 u4;
+                                if (kPW && j == NJ - 1 && kp > 1) {
+                                    // the last chunk: one Philox call draws the words of kp consecutive blocks
+                                    // (lane L: block g0 + L / nl, cell 64 (NJ - 1) + L % nl), kept in the
+                                    // wave's LDS area; block tb takes its lanes' words from there
+                                    if (tb >= pw_g0 + kp) {
+                                        pw_g0 = tb;
+                                        const int pk_b = (int)(__umul24((uint32_t)L, nl_inv) >> 16), pk_c = L - pk_b * nl;
+                                        const uint4 w4 = philox(
+                                            make_uint4((uint32_t)(64 * (NJ - 1) + pk_c) + 65536u * (uint32_t)(tb + pk_b),
+                                                       (uint32_t)s, (uint32_t)r, d.inst_id),
+                                            a.seed, 0u);
+                                        *(lds_u32x4 *)(pwd + 4 * L) = u32x4{w4.x, w4.y, w4.z, w4.w};
+                                    }
+                                    const int src = L < nl ? (tb - pw_g0) * nl + L : 0;   // other lanes: padding
+                                    const u32x4 w4 = *(const lds_u32x4 *)(pwd + 4 * src);
+                                    u4 = make_uint4(w4.x, w4.y, w4.z, w4.w);
+                                } else {
+                                    u4 = philox(make_uint4((uint32_t)(64 * j + L) + 65536u * (uint32_t)tb, (uint32_t)s,
+                                                           (uint32_t)r, d.inst_id),
+                                                a.seed, 0u);
+                                }
                                 const uint32_t uw[4] = {u4.x, u4.y, u4.z, u4.w};
                                 // unconditional reads (index 0 where no draw happens) issue together
                                 uint32_t th[4];

@@ -733,8 +733,10 @@ static size_t ylds_pc_lds_bytes(const uavq_plan *pl, int m, int wpb) {
 
 static size_t factored_lds_bytes(const uavq_plan *pl, int m, int cls) {
     if (cls > kByteChunks) return 4 * (size_t)pl->thr_stride + 16;   // costs stay in global memory
-    // + 64: cost-row reads of lanes past m run up to 63 bytes beyond D
-    return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64;
+    // + 64: cost-row reads of lanes past m run up to 63 bytes beyond D; + 1 KB per wave for the block-tested
+    // sweep's packed draw words (two and three chunks)
+    const size_t pw = cls >= 2 && cls <= 3 && !pl->generic_chunk ? 1024 * (size_t)pl->waves_per_block[cls] : 0;
+    return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64 + pw;
 }
 
 static int class_mmax(const uavq_plan *pl, int cls) {
