@@ -132,7 +132,8 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
         sD = lsm + 4 * Ts;
         sdep = sD + (int)al16((size_t)m * m);
     }
-    // the per-wave words of the last chunk's packed draws (two and three chunks, costs in LDS): 64 lanes x uint4
+    // the per-wave words of the last chunk's packed draws (two and three chunks, costs in LDS, when the launch
+    // gives the 1 KB per wave): 64 lanes x uint4
     constexpr bool kPW = NJ <= 3 && !DG;
     lds_u32 *const pwd = (lds_u32 *)(lsm + 4 * Ts + (DG ? 16 : (int)(al16((size_t)m * m) + al16((size_t)m) + 64)) +
                                      1024 * wave);
@@ -475,7 +476,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                                 }
                                 if (!ballot64(any)) continue;
                                 uint4 u4;
-                                if (kPW && j == NJ - 1 && kp > 1) {
+                                if (kPW && a.pw && j == NJ - 1 && kp > 1) {
                                     // the last chunk: one Philox call draws the words of kp consecutive blocks
                                     // (lane L: block g0 + L / nl, cell 64 (NJ - 1) + L % nl), kept in the
                                     // wave's LDS area; block tb takes its lanes' words from there

@@ -53,6 +53,7 @@ struct uavq_plan {
     int32_t prepared = 0, cu_count = 0;
     int32_t max_blocks[uavq::kMaxChunks + 2] = {};   // resident blocks per CU of each class's kernel
     size_t lds_class[uavq::kMaxChunks + 2] = {};
+    int32_t pw_class[uavq::kMaxChunks + 2] = {};   // the class's block-tested sweep keeps packed draw words in LDS
     int32_t ylds_w1 = 0;         // the m <= 64 sweep runs at one wave per SIMD (launch fits the chip)
     int32_t ylds_pc = 0;         // ... with a cut-producing wave beside each replica's wave
     int32_t no_producer = 0;     // UAVQ_VARIANT_NOPRODUCER

@@ -79,6 +79,7 @@ struct KArgs {
     uint32_t *inst_best_state;
     int64_t *inst_state_off;    // per instance: word offset of its best state in inst_best_state
     uint64_t *attempts;         // per replica: flips attempted (N per sweep run), optional
+    int32_t pw;                 // block-tested sweep: the dynamic LDS holds 1 KB per wave for packed draw words
 };
 
 }  // namespace uavq

@@ -731,12 +731,12 @@ static size_t ylds_pc_lds_bytes(const uavq_plan *pl, int m, int wpb) {
     return ylds_lds_bytes(pl, m, wpb) + (size_t)wpb * 2 * ((m + 3) / 4) * 64 * 8 + (size_t)wpb * 4 * 4;
 }
 
-static size_t factored_lds_bytes(const uavq_plan *pl, int m, int cls) {
+static size_t factored_lds_bytes(const uavq_plan *pl, int m, int cls, bool pw) {
     if (cls > kByteChunks) return 4 * (size_t)pl->thr_stride + 16;   // costs stay in global memory
     // + 64: cost-row reads of lanes past m run up to 63 bytes beyond D; + 1 KB per wave for the block-tested
-    // sweep's packed draw words (two and three chunks)
-    const size_t pw = cls >= 2 && cls <= 3 && !pl->generic_chunk ? 1024 * (size_t)pl->waves_per_block[cls] : 0;
-    return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64 + pw;
+    // sweep's packed draw words (two and three chunks), when asked for
+    return 4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 64 +
+           (pw ? 1024 * (size_t)pl->waves_per_block[cls] : 0);
 }
 
 static int class_mmax(const uavq_plan *pl, int cls) {
@@ -794,15 +794,31 @@ static int prepare(const uavq_plan *cpl) {
         if (pl->dense || pl->class_begin[cls + 1] <= pl->class_begin[cls]) continue;
         const int mmax = class_mmax(pl, cls), wpb = pl->waves_per_block[cls];
         const bool pc = cls == 1 && use_ylds(pl) && pl->ylds_pc;
-        const size_t lds = pc ? ylds_pc_lds_bytes(pl, mmax, wpb)
-                              : (cls == 1 && use_ylds(pl)) ? ylds_lds_bytes(pl, mmax, wpb)
-                                                           : factored_lds_bytes(pl, mmax, cls);
+        size_t lds = pc ? ylds_pc_lds_bytes(pl, mmax, wpb)
+                        : (cls == 1 && use_ylds(pl)) ? ylds_lds_bytes(pl, mmax, wpb)
+                                                     : factored_lds_bytes(pl, mmax, cls, false);
         if (lds > 160 * 1024)
             return set_error(UAVQ_ETOOBIG, "anneal: LDS need %zu bytes (m = %d, Dmax = %d)", lds, mmax, pl->Dmax);
         const void *k = class_kernel(pl, cls);
         UAVQ_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         int nb = 0;
         UAVQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, (pc ? 128 : 64) * wpb, lds));
+        pl->pw_class[cls] = 0;
+        if (cls >= 2 && cls <= 3 && !pl->generic_chunk) {
+            // the packed draw words' LDS only where it leaves the resident workgroups per CU as they are
+            const size_t lds_pw = factored_lds_bytes(pl, mmax, cls, true);
+            int nb_pw = 0;
+            if (lds_pw <= 160 * 1024) {
+                UAVQ_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_pw));
+                UAVQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb_pw, k, 64 * wpb, lds_pw));
+            }
+            if (nb_pw >= nb) {
+                lds = lds_pw;
+                pl->pw_class[cls] = 1;
+            } else {
+                UAVQ_HIP(hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+            }
+        }
         pl->max_blocks[cls] = std::max(nb, 1);
         pl->lds_class[cls] = lds;
     }
@@ -846,6 +862,7 @@ static int launch_class(const uavq_plan *pl, KArgs a, int cls, hipStream_t st) {
     const bool timed = pl->timing && !pl->graph;
     if (timed) UAVQ_HIP(hipEventRecord((hipEvent_t)pl->ev[2 * cls], st));
     const size_t lds = pl->lds_class[cls];
+    a.pw = pl->pw_class[cls];
     const void *kern = class_kernel(pl, cls);
     const int threads = (cls == 1 && use_ylds(pl) && pl->ylds_pc ? 128 : 64) * wpb;
     void *kargs[] = {&a};
