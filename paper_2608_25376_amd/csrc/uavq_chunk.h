@@ -356,16 +356,18 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
             bool spec = true;
             // one-cell steps: bit L of tmk[j] is set iff step 64 j + L + 1 holds exactly one cell (steps past m
             // hold none), so that the block tests take a shift and a compare; rebuilt after each walked block
+            // (up to seven chunks: at nine, the masks' scalar registers cost more in spills than they save)
+            constexpr bool kMask = NJ <= 7;
             uint64_t tmk[NJ];
 #pragma unroll
-            for (int j = 0; j < NJ; j++) tmk[j] = ballot64((si[j] & 0xffffu) == 1u);
+            for (int j = 0; j < NJ; j++) tmk[j] = kMask ? ballot64((si[j] & 0xffffu) == 1u) : 0ull;
             bool eager = false;   // the last walked block drew in every chunk (hot): draw this block's up front
             // The state is a permutation (every step one cell, every cell one step) and dcut <= 2P - 2 w_max:
             // a set site's dE = 4P - (Y_{t-1} + Y_{t+1} + 2P) >= 2P - 2 w_max >= dcut is never below the cut, and
             // its v = Y_{t-1} + Y_{t+1} + 2P >= dcut never passes for a clear site's.  Quiet blocks then need only
             // min v >= dcut.  Cleared for the rest of the sweep by an accepted flip.
             bool perm = false;
-            if (dcut <= twoP - 2 * d.wmax) {
+            if (kMask && dcut <= twoP - 2 * d.wmax) {
                 bool ok = true;
 #pragma unroll
                 for (int j = 0; j < NJ; j++) ok &= 64 * j + L >= m || (KC[j] == twoP && (si[j] & 0xffffu) == 1u);
@@ -396,7 +398,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
 #pragma unroll
             for (int jt = 0; jt < NJ; jt++) {
                 int q0 = 0;
-                if (perm) {
+                if (kMask && perm) {
                     // The common case once the state is a permutation: blocks of one-cell steps whose next four
                     // steps (same chunk) hold one cell each too, quiet by the min test.  The window moves on and
                     // nothing else changes (what the general loop below does for them, in fewer steps); the
@@ -433,7 +435,13 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     // ---- quiet-block test (every step of the block holds one cell: the
                     // low halves of the four summaries are all 1)
                     bool done = false;
-                    const bool tours = spec && ((tmk[jt] >> q0) & 0xfull) == 0xfull;
+                    bool tours = spec;
+                    if constexpr (kMask) {
+                        tours = tours && ((tmk[jt] >> q0) & 0xfull) == 0xfull;
+                    } else {
+                        const uint32_t s_or = sx[0] | sx[1] | sx[2] | sx[3], s_and = sx[0] & sx[1] & sx[2] & sx[3];
+                        tours = tours && t0 + 3 <= m && (s_or & 0xfffe) == 0 && (s_and & 1);
+                    }
                     // R_t = 1: dE = v for x = 0 and 4P - v for x = 1, v = Y_{t-1} + Y_{t+1} + 2P C_c;
                     // x = 1 exactly at the lane whose cell the summary names
                     auto dEq = [&](int i, int j) {
@@ -696,7 +704,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                         eager = drawn == (1u << NJ) - 1u && !spec;
                         // the masks again from the summaries (not held over the walk, whose registers are scarce)
 #pragma unroll
-                        for (int j = 0; j < NJ; j++) tmk[j] = ballot64((si[j] & 0xffffu) == 1u);
+                        for (int j = 0; j < NJ; j++) tmk[j] = kMask ? ballot64((si[j] & 0xffffu) == 1u) : 0ull;
                     }
                     // shift the window by four steps; the new rows (steps t0+5 .. t0+8:
                     // lanes q0+5.. of chunk jt, or of chunk jt+1 past lane 63) were not
@@ -719,13 +727,20 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             }
                         }
                         // steps t0+5 .. t0+8 are lanes q0+5 .. q0+8 of chunk jt, past 63 of chunk jt + 1
-                        const int sh = q0 + 5;   // 5 .. 65
-                        uint64_t nb = sh < 64 ? tmk[jt] >> sh : 0ull;
-                        if (jt + 1 < NJ && sh > 60) {
-                            const uint64_t hi = tmk[jt + 1 < NJ ? jt + 1 : jt];
-                            nb = sh < 64 ? nb | (hi << (64 - sh)) : hi >> (sh - 64);
+                        bool ntours;
+                        if constexpr (kMask) {
+                            const int sh = q0 + 5;   // 5 .. 65
+                            uint64_t nb = sh < 64 ? tmk[jt] >> sh : 0ull;
+                            if (jt + 1 < NJ && sh > 60) {
+                                const uint64_t hi = tmk[jt + 1 < NJ ? jt + 1 : jt];
+                                nb = sh < 64 ? nb | (hi << (64 - sh)) : hi >> (sh - 64);
+                            }
+                            ntours = (nb & 0xfull) == 0xfull;
+                        } else {
+                            const uint32_t l_or = sv[0] | sv[1] | sv[2] | sv[3], l_and = sv[0] & sv[1] & sv[2] & sv[3];
+                            ntours = t0 + 8 <= m && (l_or & 0xfffe) == 0 && (l_and & 1);
                         }
-                        if ((nb & 0xfull) == 0xfull) {
+                        if (ntours) {
                             // four one-cell steps: their cost rows
 #pragma unroll
                             for (int k = 0; k < 4; k++) {
