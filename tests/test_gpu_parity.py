@@ -326,6 +326,39 @@ def test_largest_penalty(U, oracle_lib, rows, cols, dens, inst, R):
         U.qubo_build(rows, cols, nofly=g.nofly, penalty=P + 1)
 
 
+@pytest.mark.parametrize("side", [10, 12])
+def test_block_tested_shapes_and_packed_words(U, side):
+    """Two and three chunks (m = 99, 143): four, eight and sixteen replicas
+    per workgroup give identical bytes in every output, and equal the generic
+    walk.  The last chunk's packed draw words sit in LDS only where that
+    leaves the resident workgroups per CU unchanged (on the 12x12 field: off
+    at four replicas per workgroup, on at eight), so both paths are compared.
+    A quarter of the replicas start from tours (the quiet loop of a
+    permutation state runs once the cut is low enough), over a whole schedule."""
+    g = inputs.grid(side, side, 0.0, seed=9, inst=side)
+    m = g.n_free
+    R, S = 64, 600
+    rng = np.random.default_rng(side)
+    x0 = np.zeros((R, m * m), np.uint8)
+    for r in range(R):
+        X = np.zeros((m, m), np.uint8)
+        X[np.arange(m), rng.permutation(m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = (np.arange(R) % 4 == 0).astype(np.uint8)
+    runs = {}
+    for wpb in (4, 8, 16):
+        say(f"case: block-tested {side}x{side} m={m} R={R} S={S} wpb={wpb}")
+        _, pa, runs[wpb] = gpu_anneal(U, [g], R, S, 200.0, 0.5, 3, wpb=wpb, init_x=[x0], seeded=seeded)
+        assert pa.kernel_name((m + 63) // 64) == f"k_sweep_chunk<{(m + 63) // 64}>"
+    say(f"case: generic walk {side}x{side} m={m}")
+    _, _, rg = gpu_anneal(U, [g], R, S, 200.0, 0.5, 3, init_x=[x0], seeded=seeded, generic_chunk=True)
+    for wpb in (4, 16):
+        for k in runs[8]:
+            assert np.array_equal(runs[wpb][k], runs[8][k]), (wpb, k)
+    for k in runs[8]:
+        assert np.array_equal(runs[8][k], rg[k]), k
+
+
 @pytest.mark.parametrize("side,dens,inst", [(9, 0.1, 80), (10, 0.0, 81), (12, 0.0, 82), (13, 0.1, 83), (14, 0.05, 84),
                                            (15, 0.05, 85), (16, 0.0, 86), (18, 0.05, 88), (19, 0.0, 89),
                                            (20, 0.0, 91), (22, 0.0, 92), (24, 0.0, 93)])
