@@ -551,6 +551,9 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                             have_cut = (1u << NJ) - 1u;
                         }
                         uint32_t drawn = 0;   // bit j: a site of chunk j needed a draw in this block
+                        // the walk is a chain of dependent ballots: it issues first on its SIMD, and the other
+                        // waves' Philox stretches fill the gaps
+                        __builtin_amdgcn_s_setprio(2);
 #pragma unroll
                         for (int i = 0; i < 4; i++) {
                             const int t = t0 + i;
@@ -702,6 +705,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                         spec = nacc_s == acc_before;
                         perm = perm && spec;
                         eager = drawn == (1u << NJ) - 1u && !spec;
+                        __builtin_amdgcn_s_setprio(0);
                         // the masks again from the summaries (not held over the walk, whose registers are scarce)
 #pragma unroll
                         for (int j = 0; j < NJ; j++) tmk[j] = kMask ? ballot64((si[j] & 0xffffu) == 1u) : 0ull;
