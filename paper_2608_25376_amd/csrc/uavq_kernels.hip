@@ -444,6 +444,9 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
                     // Sequential walk.  Until a site of the block needs a draw the
                     // cut is 1 (accept iff dE <= 0); from then on the exact cuts of
                     // the block's four steps make every acceptance test one compare.
+                    // Its chain of dependent ballots issues first on the SIMD (without
+                    // the producer: the other waves' speculative passes fill the gaps).
+                    if (!PC) __builtin_amdgcn_s_setprio(2);
                     bool have_cut = PC;   // PC: always the exact cuts
                     int cut0 = 1, cut1 = 1, cut2 = 1, cut3 = 1;
                     if (PC) {
@@ -533,6 +536,7 @@ __device__ __forceinline__ void ylds_item(const KArgs &a, int itx, uint8_t *smem
 #pragma unroll
                     for (int i = 0; i < 4; i++)
                         if (t0 + i <= m) Yw[(t0 + i - 1) * 64 + L] = (uint16_t)Yv[i + 1];
+                    if (!PC) __builtin_amdgcn_s_setprio(0);
                 }
                 Yv0 = Yv[4];
                 Yv1 = Yv[5];
