@@ -428,6 +428,10 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                     const int t0 = 64 * jt + q0 + 1;
                     if (t0 > m) break;
                     const int tb = (t0 - 1) >> 2;
+                    // wave priority: the block's tests and walk are chains of dependent instructions and issue
+                    // before other waves' Philox stretches (the eager draws and the draws-only test), which fill
+                    // the gaps
+                    __builtin_amdgcn_s_setprio(1);
                     uint32_t sx[4];   // summaries of the block's steps
 #pragma unroll
                     for (int i = 0; i < 4; i++) sx[i] = rl(si[jt], q0 + i);
@@ -468,6 +472,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                         if (!ballot64(mn < dcut)) {
                             done = true;   // nothing below the cut: every site rejected without a draw
                         } else if (!ballot64(mn <= 0)) {
+                            __builtin_amdgcn_s_setprio(0);   // the draws: a long stretch with ample parallel work
                             // only draws: take the chunks' words; finished if none accepts
                             bool acc = false;
                             uint32_t nd = 0;
@@ -529,6 +534,7 @@ __device__ __forceinline__ void chunk_item(const KArgs &a, int itx, uint8_t *sme
                         uint32_t have_cut = 0;   // bit j: chunk j's cuts of this block are known
                         uint32_t cutp[NJ][2];
                         if (eager) {
+                            __builtin_amdgcn_s_setprio(0);   // a long stretch with ample parallel work
                             // every chunk is likely to need its words: draw them all here, in one
                             // branch-free stretch (the cuts depend on the words and the table only)
 #pragma unroll
