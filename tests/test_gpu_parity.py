@@ -326,6 +326,40 @@ def test_largest_penalty(U, oracle_lib, rows, cols, dens, inst, R):
         U.qubo_build(rows, cols, nofly=g.nofly, penalty=P + 1)
 
 
+@pytest.mark.parametrize("T", [5.0, 20.0])
+def test_permutation_quiet_loop_against_oracle(U, oracle_lib, T):
+    """12x12 field (m = 143) at a constant temperature, every replica against
+    the oracle.  Half the replicas start from tours: at T = 5 the cut (about
+    111) is below 2P - 2 w_max (312), so from the first sweep their quiet
+    blocks take the permutation state's min test and its loop; at T = 20 (cut
+    about 444) they take the general block test, where only a step's set site
+    can fall below the cut.  The other half start random and reach tours
+    during the run."""
+    g = inputs.grid(12, 12, 0.0, seed=9, inst=12)
+    m = g.n_free
+    R, S = 16, 200
+    rng = np.random.default_rng(12)
+    x0 = np.zeros((R, m * m), np.uint8)
+    for r in range(R):
+        X = np.zeros((m, m), np.uint8)
+        X[np.arange(m), rng.permutation(m)] = 1
+        x0[r] = X.reshape(-1)
+    seeded = (np.arange(R) < R // 2).astype(np.uint8)
+    say(f"case: permutation quiet loop 12x12 m={m} R={R} S={S} T={T}")
+    qs, plan, res = gpu_anneal(U, [g], R, S, T, T, 8, init_x=[x0], seeded=seeded, check_E=True)
+    gi = split(U, qs, plan, res)[0]
+    assert np.array_equal(gi["check_E"], gi["final_E"])
+    o = _oracle_for(oracle_lib, g)
+    reps = list(range(R))
+    seeded_reps = [r for r in reps if seeded[r]]
+    random_reps = [r for r in reps if not seeded[r]]
+    orc_s = oracle_lib.anneal(o, S, T, T, 8, g.inst_id, seeded_reps, init_x=x0[seeded_reps], threads=8)
+    compare_replicas(gi, orc_s, seeded_reps, f"12x12 T={T} seeded")
+    orc_r = oracle_lib.anneal(o, S, T, T, 8, g.inst_id, random_reps, threads=8)
+    compare_replicas(gi, orc_r, random_reps, f"12x12 T={T} random")
+    check_reduce(oracle_lib, gi, R, f"12x12 T={T} reduce")
+
+
 @pytest.mark.parametrize("side", [10, 12])
 def test_block_tested_shapes_and_packed_words(U, side):
     """Two and three chunks (m = 99, 143): four, eight and sixteen replicas
