@@ -517,6 +517,19 @@ int uavq_plan_create(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *
     for (int c = 0; c <= kMaxChunks + 1; c++) pl->class_begin[c] = 0;
     for (int cls = 1; cls <= kMaxChunks; cls++) {
         int wpb = p->waves_per_block ? p->waves_per_block : default_waves_per_block(cls);
+        if (cls == 1 && !p->waves_per_block) {
+            // m <= 64 with more replicas than the chip has SIMDs (so not one wave per SIMD): twelve replicas share
+            // a workgroup's table row and cost rows, three waves per SIMD instead of two, where their LDS fits
+            // (the 256-field batch's m <= 64 kernel: 334 -> 298 ms)
+            int64_t n1 = 0;
+            int m1 = 0;
+            for (int32_t i = 0; i < n_inst; i++)
+                if (inst_class(q[i], dense) == 1) {
+                    n1 += R;
+                    m1 = std::max(m1, q[i]->m);
+                }
+            if (n1 > kSimdsPerChip && ylds_lds_bytes_for((size_t)pl->thr_stride, m1, 12) <= 160 * 1024) wpb = 12;
+        }
         if (p->tune && p->tune->waves_per_block[cls] > 0) wpb = p->tune->waves_per_block[cls];
         if (cls >= 4 && wpb > kWideMaxWaves) wpb = kWideMaxWaves;   // those kernels' block limit
         if (wpb < 1 || wpb > 16) {

@@ -25,6 +25,15 @@ struct uavq_qubo {
     std::vector<int16_t> J;      // N*N dense couplings (optional)
 };
 
+// LDS bytes of a workgroup of the m <= 64 sweep with wpb replicas: the table row, D and the start-cell costs as
+// bytes, the signed cost rows (2m rows of 64 int16), and per replica the travel rows of steps 1..m plus 8 boundary
+// rows (64 int16 each) and 68 step counts
+inline size_t ylds_lds_bytes_for(size_t thr_stride, int m, int wpb) {
+    auto a16 = [](size_t v) { return (v + 15) & ~(size_t)15; };
+    return a16(4 * thr_stride + a16((size_t)m * m) + a16((size_t)m) + 256 * (size_t)m + (size_t)wpb * 64 * (m + 8) * 2) +
+           (size_t)wpb * 68 * 4;
+}
+
 struct uavq_plan {
     uavq_anneal_params p;
     int32_t n_inst, S, Dmax, thr_stride;

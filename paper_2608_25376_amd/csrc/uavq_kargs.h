@@ -15,6 +15,7 @@ constexpr int kMaxChunks = 9;
 constexpr int kByteChunks = 6;
 constexpr int kMaxM = 64 * kMaxChunks;
 constexpr int kWideMaxWaves = 4;   // waves per block of the kernels of classes 4..kMaxChunks
+constexpr int kSimdsPerChip = 1024;   // MI355X: 256 CUs x 4 SIMDs
 
 int set_error(int code, const char *fmt, ...);
 

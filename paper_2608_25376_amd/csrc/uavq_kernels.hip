@@ -723,10 +723,7 @@ __global__ void k_count_mismatch(const int64_t *E, const int64_t *E_check, uint3
 
 // ------------------------------------------------------------- launchers --
 static size_t ylds_lds_bytes(const uavq_plan *pl, int m, int wpb) {
-    // per replica: travel rows of steps 1..m plus 8 boundary rows, 64 int16 each, and 68 step counts
-    return al16(4 * (size_t)pl->thr_stride + al16((size_t)m * m) + al16((size_t)m) + 256 * (size_t)m +
-                (size_t)wpb * 64 * (m + 8) * 2) +
-           (size_t)wpb * 68 * 4;
+    return ylds_lds_bytes_for((size_t)pl->thr_stride, m, wpb);
 }
 
 // + the producer/consumer pairs' cut buffers (two sweeps of ceil(m/4) blocks of
@@ -1316,7 +1313,7 @@ int uavq_autotune(const uavq_qubo *const *q, int32_t n_inst, const uint32_t *ins
     // Chunk classes launch one after another, so each class's shape is chosen
     // on its own kernel's time (events around each class's launch); the
     // variant only concerns class 1.
-    const int wpbs[] = {1, 2, 4, 8, 16};
+    const int wpbs[] = {1, 2, 4, 8, 12, 16};   // 12: three waves per SIMD for m <= 64 where their LDS fits
     const uint32_t variants[] = {0u, UAVQ_VARIANT_ROWMASK, UAVQ_VARIANT_NOPRODUCER};
     hipStream_t st = nullptr;
     UAVQ_HIP(hipStreamCreate(&st));
